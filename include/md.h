@@ -1,0 +1,280 @@
+/*
+ * md.h - C ABI of the MI355X (gfx950) short-range molecular-dynamics hot path.
+ *
+ * The library integrates Newton's equations m_i r_i'' = f_i = -grad_i U
+ * (MDcraft paper, Sec. 1.5, eq. 1.5) with velocity Verlet for atoms that
+ * interact through short-range potentials (Sec. 1.6: Lennard-Jones and
+ * single-element EAM), using a cell grid and Verlet neighbour lists with a
+ * skin (Sec. 1.4, eq. 1.2) in periodic or walled boxes (Sec. 1.5).
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless the comment says "host".  The caller
+ *     owns all memory; the library never allocates.  Sizes come from the
+ *     md_*_bytes() queries.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is the
+ *     default stream) and is stream-ordered.  No entry point synchronises
+ *     except md_read_flags().  Calls on distinct streams with distinct buffers
+ *     are independent; calls that share a control block must be ordered.
+ *   - Units: angstrom, eV, ps, u (atomic mass), K.  Accelerations use
+ *     1 eV/(u angstrom) = 9648.5332157 angstrom/ps^2.
+ *   - Atom arrays hold n_atoms entries of all boxes of a batch end to end.
+ *     Positions are `double4` records {x, y, z, w} ([n_atoms][4] doubles); the
+ *     w slot is library scratch (the EAM passes store F'(rhobar) there).
+ *     Velocities and forces are structure-of-arrays [3][n_atoms] (x block, y
+ *     block, z block).  Positions and velocities are always FP64; forces are
+ *     FP64 or FP32 as the precision argument says.
+ *   - After md_bin_cells the atoms are in cell order inside each box; id[]
+ *     carries the caller's original atom ids along with the permutation.
+ *     Positions are wrapped into the box at that point only; between rebuilds
+ *     an atom may stand outside its periodic box by at most half the skin.
+ *   - Return values are md_status codes.  Argument errors return at once and
+ *     enqueue nothing.  Conditions detected on the device set sticky bits in
+ *     the control block; md_read_flags() reads and maps them.
+ */
+#ifndef MD950_MD_H
+#define MD950_MD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MD_OK = 0,
+  MD_ERR_ARG = -1,            /* bad argument (null pointer, size, enum) */
+  MD_ERR_BOX = -2,            /* r_ns >= L/2 on a periodic axis, or an empty box */
+  MD_ERR_NEIGH_OVERFLOW = -3, /* an atom has more than max_neigh neighbours */
+  MD_ERR_TABLE_RANGE = -4,    /* r below a table's start or rhobar outside the F table */
+  MD_ERR_WALL = -5,           /* an atom left a non-periodic extent */
+  MD_ERR_NONFINITE = -6,      /* a position became NaN or infinite */
+  MD_ERR_HIP = -7,            /* a HIP runtime call failed */
+  MD_ERR_WORKSPACE = -8       /* workspace or capacity too small */
+} md_status;
+
+/* Device flag bits (md_read_flags output). */
+#define MD_FLAG_NEIGH_OVERFLOW 1
+#define MD_FLAG_TABLE_RANGE 2
+#define MD_FLAG_WALL 4
+#define MD_FLAG_NONFINITE 8
+
+typedef enum { MD_FP64 = 0, MD_FP32 = 1 } md_precision; /* MD_FP32: FP32 pair math and
+                                                          force accumulation, FP64
+                                                          positions/integration/reductions */
+
+typedef enum { MD_ALWAYS = 0, MD_IF_FLAGGED = 1 } md_rebuild_mode;
+typedef enum { MD_KICK_DRIFT = 0, MD_KICK = 1 } md_verlet_phase;
+
+/* Orthorhombic box [lo, lo + len) per axis (host struct). */
+typedef struct md_box {
+  double lo[3];
+  double len[3];
+  int periodic[3];
+  int pad;
+} md_box;
+
+/* Per-box cell grid and bookkeeping, produced by md_plan (device array of n_rep). */
+typedef struct md_domain {
+  double lo[3];
+  double len[3];
+  double inv_len[3];
+  double inv_w[3]; /* cells per unit length, nc / len */
+  int nc[3];
+  int periodic[3];
+  int cell_off; /* first global cell index of this box */
+  int atom_off; /* first atom */
+  int n_atoms;
+  int tile_off; /* first work tile */
+  int n_tiles;
+  int pad;
+} md_domain;
+
+/* A work tile: up to tile_atoms consecutive atoms of one box. */
+typedef struct md_tile {
+  int rep;
+  int first;
+  int count;
+  int pad;
+} md_tile;
+
+/* A batch of independent boxes laid end to end.  A single system is n_rep = 1. */
+typedef struct md_batch {
+  int n_rep;
+  int n_atoms;
+  int n_cells;
+  int n_tiles;
+  int tile_atoms;
+  int pad;
+  double r_ns;              /* neighbour search radius the grids were planned for */
+  const md_domain* domains; /* device [n_rep] */
+  const md_tile* tiles;     /* device [n_tiles] */
+} md_batch;
+
+/* Neighbour-list layout: padded ELL, strided for `lanes` lanes per atom.  Entry
+ * n of atom i lives at index ((n / lanes) * n_atoms_pad + i) * lanes + n % lanes
+ * of an int32 array of max_neigh * n_atoms_pad entries, n_atoms_pad = n_atoms
+ * rounded up to 64.  Entries are atom indices in the current (cell) order. */
+typedef struct md_nlist {
+  int* neigh;   /* device [max_neigh * n_atoms_pad] */
+  int* nneigh;  /* device [n_atoms] */
+  int max_neigh;/* multiple of lanes */
+  int lanes;    /* 1, 2, 4, 8 or 16 */
+} md_nlist;
+
+/* Uniform cubic B-spline on breakpoints x_lo + k h (k = 0..ncoef-3): ncoef
+ * coefficients (FP64, device). */
+typedef struct md_spline {
+  const double* coef;
+  int ncoef;
+  int pad;
+  double x_lo;
+  double h;
+} md_spline;
+
+/* Single-element EAM: pair phi(r), density rho(r), embedding F(rhobar); phi and rho
+ * must share one grid.  Interaction for r < r_cut only. */
+typedef struct md_eam {
+  md_spline phi, rho, emb;
+  double r_cut;
+} md_eam;
+
+typedef struct md_lj {
+  double eps;
+  double sigma;
+  double r_cut; /* energy shifted by U(r_cut); force unshifted */
+} md_lj;
+
+/* A piston plane at z0 + v t along `axis`, reflecting specularly in its frame,
+ * and a static top wall at top (Sec. 1.5, hard walls). */
+typedef struct md_walls {
+  int enabled;
+  int axis;
+  double piston_z0;
+  double piston_v;
+  double top;
+} md_walls;
+
+/* Per-step thermodynamic record per box: {E_pot, W_xx, W_yy, W_zz, W_xy, W_xz,
+ * W_yz, K} in eV, W the pair virial 1/2 sum_ij r_ij f_ij (Appendix), K the kinetic
+ * energy (eq. 1.3). */
+#define MD_EV_LEN 8
+
+/* ---------------------------------------------------------------------------
+ * Set-up (host)
+ * ------------------------------------------------------------------------- */
+
+/* Count the cells and tiles a batch needs.  Host arrays: boxes[n_rep],
+ * atom_off[n_rep + 1].  Returns MD_ERR_BOX if a periodic length is not above
+ * 2 r_ns (the minimum image of every neighbour must be unique). */
+int md_plan_count(int n_rep, const md_box* boxes, const int* atom_off, double r_ns,
+                  int tile_atoms, int* n_cells, int* n_tiles);
+
+/* Fill the host arrays domains[n_rep] and tiles[n_tiles] (sizes from
+ * md_plan_count).  The cell grid of each box has nc = max(1, floor(len / r_ns))
+ * cells per axis, so a cell edge is at least r_ns (Sec. 1.4: a virtual grid
+ * with cell edge R).  The caller copies both arrays to the device and fills an
+ * md_batch with them. */
+int md_plan(int n_rep, const md_box* boxes, const int* atom_off, double r_ns, int tile_atoms,
+            md_domain* domains, md_tile* tiles);
+
+/* Bytes of the device control block (step counter, rebuild flag, error flags,
+ * reduction counters).  md_ctl_init clears it (by a kernel, graph safe). */
+size_t md_ctl_bytes(void);
+int md_ctl_init(void* ctl, void* stream);
+
+/* Bytes of workspace md_bin_cells and the force passes need for this batch. */
+size_t md_workspace_bytes(const md_batch* b);
+
+/* Bytes of the packed interval tables md_eam_prepare writes. */
+size_t md_eam_table_bytes(const md_eam* p, md_precision prec);
+
+/* Complete (clamped) cubic spline fit on the device: given K samples y[k] of a
+ * function at x_lo + k h and its end slopes, write the K + 2 B-spline
+ * coefficients that interpolate every sample and match both slopes (the form
+ * in which a tabulated potential file is turned into a spline; Sec. 3.3). */
+int md_spline_fit(const double* y, int K, double h, double dy_lo, double dy_hi, double* coef,
+                  void* stream);
+
+/* Convert EAM B-spline coefficients into per-interval polynomial tables in the
+ * given precision (values and derivatives in Horner form).  Call again whenever
+ * the coefficients change. */
+int md_eam_prepare(const md_eam* p, md_precision prec, void* table, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Hot path (Sec. 1.4 - 1.6)
+ * ------------------------------------------------------------------------- */
+
+/* Wrap positions into their boxes, bin atoms into the cell grid (a counting
+ * sort, Sec. 1.4 "bucket sort"), and permute pos, vel and id into cell order
+ * (order inside a cell: ascending id).  Sets pos_ref = pos (the reference of
+ * the displacement check).  cell_start[n_cells + 1] receives the first atom of
+ * each cell.  With MD_IF_FLAGGED the kernels do nothing unless the last
+ * md_verlet_step found a displacement above half the skin. */
+int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos, double* vel, int* id,
+                 double* pos_ref, int* cell_start, void* ws, void* ctl, void* stream);
+
+/* Build the full Verlet list {j != i : |r_ij| < r_ns} (Sec. 1.4, eq. 1.2 with
+ * r_ns = r_c + skin) by scanning the 3x3x3 block of cells around each atom's
+ * cell (de-duplicated when a box has fewer than 3 cells on an axis).  Distances
+ * use the minimum image in FP64 with no fused multiply-add, so the set equals
+ * the brute-force definition bit for bit.  Sets MD_FLAG_NEIGH_OVERFLOW when an
+ * atom has more than max_neigh neighbours. */
+int md_build_neighbors(const md_batch* b, md_rebuild_mode mode, const double* pos,
+                       const int* cell_start, const md_nlist* nl, void* ctl, void* stream);
+
+/* Lennard-Jones forces (eq. 1.6), energy and virial.  force is [3][n] FP64 or
+ * FP32.  If vel is not NULL the trailing half kick v += half_dt f / m is applied
+ * and the kinetic energy is reduced.  If ev is not NULL the per-box record
+ * {E, W[6], K} is written to ev[(step % ev_cap) * n_rep + rep] (step = the
+ * control block's step counter). */
+int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec, const double* pos,
+                 const md_nlist* nl, void* force, double* vel, double inv_mass, double half_dt,
+                 double* ev, int ev_cap, void* ws, void* ctl, void* stream);
+
+/* EAM forces: a density pass (rhobar_i = sum_j rho(r_ij), F(rhobar_i),
+ * F'(rhobar_i), the energy) then a force pass
+ *   f_i = -sum_j [phi'(r) + (F'(rhobar_i) + F'(rhobar_j)) rho'(r)] r_ij / r,
+ * with the virial and an optional trailing half kick as in md_lj_forces.
+ * table: from md_eam_prepare in the same precision.  If saved is not NULL it
+ * receives {rhobar, F', F''} as [3][n] FP64 for md_eam_backward. */
+int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec, const void* table,
+                  const double* pos, const md_nlist* nl, void* force, double* saved,
+                  double* vel, double inv_mass, double half_dt, double* ev, int ev_cap, void* ws,
+                  void* ctl, void* stream);
+
+/* Velocity Verlet (Sec. 1.5).  MD_KICK_DRIFT: v += half_dt f/m; x += dt v; walls
+ * at t = (step + 1) dt; then the largest |x - pos_ref|^2 is compared with
+ * (half_skin)^2 and the rebuild flag set for the next md_bin_cells; the step
+ * counter advances.  MD_KICK: v += half_dt f/m only.  half_dt = dt / 2. */
+int md_verlet_step(const md_batch* b, md_verlet_phase phase, double dt, double* pos,
+                   double* vel, const void* force, md_precision prec, double inv_mass,
+                   const md_walls* walls, const double* pos_ref, double half_skin, void* ctl,
+                   void* stream);
+
+/* Vector-Jacobian product of the EAM forces with respect to the three spline
+ * coefficient vectors: grad_coef[phi | rho | F] += sum_i G_i . dF_i/dc for a
+ * cotangent G = dL/dF ([3][n] FP64).  Needs `saved` from md_eam_forces on the
+ * same positions and coefficients.  Accumulation is in FP64 and deterministic.
+ * grad_coef has phi.ncoef + rho.ncoef + emb.ncoef entries (at most 1024 in all) and is
+ * overwritten.  ws: md_backward_workspace_bytes(b, p) bytes.  The accumulation is FP64
+ * whatever `prec` the forward pass used. */
+size_t md_backward_workspace_bytes(const md_batch* b, const md_eam* p);
+int md_eam_backward(const md_batch* b, const md_eam* p, md_precision prec, const double* pos,
+                    const md_nlist* nl, const double* saved, const double* grad_force,
+                    double* grad_coef, void* ws, void* ctl, void* stream);
+
+/* Copy the control block's sticky flags and counters to host memory
+ * host_out[4] = {flags, step, n_rebuilds, max_nneigh} and synchronise the
+ * stream.  Returns the md_status of the most severe flag set (MD_OK if none). */
+int md_read_flags(const void* ctl, int* host_out, void* stream);
+
+/* Clear the sticky error flags (not the counters). */
+int md_clear_flags(void* ctl, void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* md_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MD950_MD_H */

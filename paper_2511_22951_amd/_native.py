@@ -1,0 +1,128 @@
+"""ctypes declarations of libmd950 (include/md.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmd950.so")
+
+MD_OK = 0
+MD_FP64, MD_FP32 = 0, 1
+MD_ALWAYS, MD_IF_FLAGGED = 0, 1
+MD_KICK_DRIFT, MD_KICK = 0, 1
+MD_EV_LEN = 8
+MD_TILE = 64
+FLAG_NEIGH_OVERFLOW, FLAG_TABLE_RANGE, FLAG_WALL, FLAG_NONFINITE = 1, 2, 4, 8
+
+
+class MDError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, _status_string(status), status))
+
+
+class Box(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("len", C.c_double * 3), ("periodic", C.c_int * 3),
+                ("pad", C.c_int)]
+
+
+class Domain(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("len", C.c_double * 3), ("inv_len", C.c_double * 3),
+                ("inv_w", C.c_double * 3), ("nc", C.c_int * 3), ("periodic", C.c_int * 3),
+                ("cell_off", C.c_int), ("atom_off", C.c_int), ("n_atoms", C.c_int),
+                ("tile_off", C.c_int), ("n_tiles", C.c_int), ("pad", C.c_int)]
+
+
+class Tile(C.Structure):
+    _fields_ = [("rep", C.c_int), ("first", C.c_int), ("count", C.c_int), ("pad", C.c_int)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("n_rep", C.c_int), ("n_atoms", C.c_int), ("n_cells", C.c_int),
+                ("n_tiles", C.c_int), ("tile_atoms", C.c_int), ("pad", C.c_int),
+                ("r_ns", C.c_double), ("domains", C.c_void_p), ("tiles", C.c_void_p)]
+
+
+class NList(C.Structure):
+    _fields_ = [("neigh", C.c_void_p), ("nneigh", C.c_void_p), ("max_neigh", C.c_int),
+                ("lanes", C.c_int)]
+
+
+class Spline(C.Structure):
+    _fields_ = [("coef", C.c_void_p), ("ncoef", C.c_int), ("pad", C.c_int), ("x_lo", C.c_double),
+                ("h", C.c_double)]
+
+
+class EAM(C.Structure):
+    _fields_ = [("phi", Spline), ("rho", Spline), ("emb", Spline), ("r_cut", C.c_double)]
+
+
+class LJ(C.Structure):
+    _fields_ = [("eps", C.c_double), ("sigma", C.c_double), ("r_cut", C.c_double)]
+
+
+class Walls(C.Structure):
+    _fields_ = [("enabled", C.c_int), ("axis", C.c_int), ("piston_z0", C.c_double),
+                ("piston_v", C.c_double), ("top", C.c_double)]
+
+
+_lib = None
+_vp, _i, _d, _sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+_P = C.POINTER
+
+_SIGS = {
+    "md_plan_count": (_i, [_i, _P(Box), _P(C.c_int), _d, _i, _P(C.c_int), _P(C.c_int)]),
+    "md_plan": (_i, [_i, _P(Box), _P(C.c_int), _d, _i, _P(Domain), _P(Tile)]),
+    "md_ctl_bytes": (_sz, []),
+    "md_ctl_init": (_i, [_vp, _vp]),
+    "md_workspace_bytes": (_sz, [_P(Batch)]),
+    "md_eam_table_bytes": (_sz, [_P(EAM), _i]),
+    "md_spline_fit": (_i, [_vp, _i, _d, _d, _d, _vp, _vp]),
+    "md_eam_prepare": (_i, [_P(EAM), _i, _vp, _vp]),
+    "md_bin_cells": (_i, [_P(Batch), _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "md_build_neighbors": (_i, [_P(Batch), _i, _vp, _vp, _P(NList), _vp, _vp]),
+    "md_lj_forces": (_i, [_P(Batch), _P(LJ), _i, _vp, _P(NList), _vp, _vp, _d, _d, _vp, _i, _vp,
+                          _vp, _vp]),
+    "md_eam_forces": (_i, [_P(Batch), _P(EAM), _i, _vp, _vp, _P(NList), _vp, _vp, _vp, _d, _d,
+                           _vp, _i, _vp, _vp, _vp]),
+    "md_verlet_step": (_i, [_P(Batch), _i, _d, _vp, _vp, _vp, _i, _d, _P(Walls), _vp, _d, _vp,
+                            _vp]),
+    "md_eam_backward": (_i, [_P(Batch), _P(EAM), _i, _vp, _P(NList), _vp, _vp, _vp, _vp, _vp,
+                             _vp]),
+    "md_backward_workspace_bytes": (_sz, [_P(Batch), _P(EAM)]),
+    "md_read_flags": (_i, [_vp, _P(C.c_int), _vp]),
+    "md_clear_flags": (_i, [_vp, _vp]),
+    "md_status_string": (C.c_char_p, [_i]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmd950.so is not built (run paper_2511_22951_amd/build.py); "
+                               "the MD path has no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _status_string(s):
+    try:
+        return lib().md_status_string(int(s)).decode()
+    except Exception:  # pragma: no cover
+        return "status"
+
+
+def check(status, what=""):
+    if status != MD_OK:
+        raise MDError(status, what)
+    return status

@@ -1,0 +1,298 @@
+"""Python binding of libmd950 (include/md.h).
+
+Argument marshalling only: torch provides device memory and streams, every step
+of the MD path runs in the library's HIP kernels.  Function names follow the C
+entry points (md_bin_cells, md_build_neighbors, md_lj_forces, md_eam_forces,
+md_verlet_step, md_eam_backward); the small classes below hold the buffers
+those calls take.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _native as N
+from ._native import MDError, check  # noqa: F401
+
+ACCEL = 9648.5332157  # 1 eV/(u angstrom) in angstrom/ps^2 (unit conversion for callers)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _require_cuda(device):
+    if torch.device(device).type != "cuda":
+        raise RuntimeError("the MD path runs on the GPU only (device %s)" % device)
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the MD path has no CPU fallback")
+
+
+# ----------------------------------------------------------------------------
+# Plans (cell grids and work tiles of one box or a batch of boxes)
+# ----------------------------------------------------------------------------
+def _cbox(box):
+    b = N.Box()
+    for a in range(3):
+        b.lo[a] = float(box.lo[a])
+        b.len[a] = float(box.len[a])
+        b.periodic[a] = int(box.periodic[a])
+    return b
+
+
+class Plan:
+    """md_plan for n_rep boxes with atom_counts atoms each, uploaded to the device."""
+
+    def __init__(self, boxes, atom_counts, r_ns, device="cuda"):
+        _require_cuda(device)
+        L = N.lib()
+        n_rep = len(boxes)
+        cb = (N.Box * n_rep)(*[_cbox(b) for b in boxes])
+        off = np.zeros(n_rep + 1, np.int32)
+        off[1:] = np.cumsum(np.asarray(atom_counts, np.int64))
+        coff = (C.c_int * (n_rep + 1))(*off.tolist())
+        nc, nt = C.c_int(), C.c_int()
+        check(L.md_plan_count(n_rep, cb, coff, float(r_ns), N.MD_TILE, C.byref(nc), C.byref(nt)),
+              "md_plan_count")
+        doms = (N.Domain * n_rep)()
+        tiles = (N.Tile * max(1, nt.value))()
+        check(L.md_plan(n_rep, cb, coff, float(r_ns), N.MD_TILE, doms, tiles), "md_plan")
+        self.host_domains = doms
+        self.host_tiles = tiles
+        self.atom_off = off
+        self.n_rep, self.n_atoms = n_rep, int(off[-1])
+        self.n_cells, self.n_tiles = nc.value, nt.value
+        self.r_ns = float(r_ns)
+        self.device = torch.device(device)
+        self.d_domains = torch.from_numpy(
+            np.frombuffer(bytes(doms), np.uint8).copy()).to(self.device)
+        self.d_tiles = torch.from_numpy(np.frombuffer(bytes(tiles), np.uint8).copy()).to(self.device)
+        self.c = N.Batch(n_rep, self.n_atoms, self.n_cells, self.n_tiles, N.MD_TILE, 0, self.r_ns,
+                         self.d_domains.data_ptr(), self.d_tiles.data_ptr())
+        self.cells_per_axis = [tuple(doms[r].nc) for r in range(n_rep)]
+
+    def workspace_bytes(self):
+        return int(N.lib().md_workspace_bytes(C.byref(self.c)))
+
+
+# ----------------------------------------------------------------------------
+# Neighbour list
+# ----------------------------------------------------------------------------
+class NeighborList:
+    """Padded strided ELL list (md_nlist) for `lanes` lanes per atom."""
+
+    def __init__(self, n_atoms, max_neigh=128, lanes=4, device="cuda"):
+        if max_neigh % lanes:
+            max_neigh += lanes - max_neigh % lanes
+        self.n, self.max_neigh, self.lanes = n_atoms, max_neigh, lanes
+        self.npad = (n_atoms + 63) // 64 * 64
+        self.neigh = torch.zeros(max_neigh * self.npad, dtype=torch.int32, device=device)
+        self.nneigh = torch.zeros(max(1, n_atoms), dtype=torch.int32, device=device)
+        self.c = N.NList(self.neigh.data_ptr(), self.nneigh.data_ptr(), max_neigh, lanes)
+
+    def host_lists(self):
+        """Per atom (current order) the array of neighbour indices (current order)."""
+        nn = self.nneigh.cpu().numpy()[:self.n]
+        raw = self.neigh.cpu().numpy().reshape(self.max_neigh // self.lanes, self.npad, self.lanes)
+        out = []
+        for i in range(self.n):
+            k = np.arange(nn[i])
+            out.append(raw[k // self.lanes, i, k % self.lanes].copy())
+        return out
+
+
+# ----------------------------------------------------------------------------
+# Atom state
+# ----------------------------------------------------------------------------
+class State:
+    """Device arrays of one batch: pos [n,4] (double4), vel/force/pos_ref [3,n], id [n],
+    cell_start, workspace and the control block."""
+
+    def __init__(self, plan: Plan, pos, vel, precision=N.MD_FP64, ids=None):
+        dev = plan.device
+        n = plan.n_atoms
+        pos = np.asarray(pos, np.float64).reshape(n, 3)
+        vel = np.zeros((n, 3)) if vel is None else np.asarray(vel, np.float64).reshape(n, 3)
+        p4 = np.zeros((n, 4))
+        p4[:, :3] = pos
+        self.plan = plan
+        self.n = n
+        self.precision = precision
+        self.pos = torch.from_numpy(p4).to(dev)
+        self.vel = torch.from_numpy(np.ascontiguousarray(vel.T)).to(dev)
+        fdt = torch.float32 if precision == N.MD_FP32 else torch.float64
+        self.force = torch.zeros((3, n), dtype=fdt, device=dev)
+        ids = np.arange(n, dtype=np.int32) if ids is None else np.asarray(ids, np.int32)
+        self.id = torch.from_numpy(ids.copy()).to(dev)
+        self.pos_ref = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        self.cell_start = torch.zeros(plan.n_cells + 1, dtype=torch.int32, device=dev)
+        self.ws = torch.zeros(max(256, plan.workspace_bytes()), dtype=torch.uint8, device=dev)
+        self.ctl = torch.zeros(int(N.lib().md_ctl_bytes()), dtype=torch.uint8, device=dev)
+        check(N.lib().md_ctl_init(_ptr(self.ctl), _stream()), "md_ctl_init")
+
+    # host views, ordered by original id
+    def _order(self):
+        return np.argsort(self.id.cpu().numpy(), kind="stable")
+
+    def positions(self):
+        return self.pos[:, :3].cpu().numpy()[self._order()]
+
+    def velocities(self):
+        return self.vel.t().cpu().numpy()[self._order()]
+
+    def forces(self):
+        return self.force.t().double().cpu().numpy()[self._order()]
+
+    def read_flags(self):
+        out = (C.c_int * 4)()
+        st = N.lib().md_read_flags(_ptr(self.ctl), out, _stream())
+        return st, {"flags": out[0], "step": out[1], "n_rebuilds": out[2], "max_nneigh": out[3]}
+
+    def check_flags(self, what="device flags"):
+        st, info = self.read_flags()
+        check(st, what)
+        return info
+
+    def clear_flags(self):
+        check(N.lib().md_clear_flags(_ptr(self.ctl), _stream()), "md_clear_flags")
+
+
+# ----------------------------------------------------------------------------
+# Potentials
+# ----------------------------------------------------------------------------
+def md_spline_fit(y, h, dy_lo, dy_hi, device="cuda"):
+    """Complete cubic spline fit on the device; returns K + 2 coefficients."""
+    y = torch.as_tensor(np.asarray(y, np.float64), device=device)
+    coef = torch.zeros(y.shape[0] + 2, dtype=torch.float64, device=device)
+    check(N.lib().md_spline_fit(_ptr(y), int(y.shape[0]), float(h), float(dy_lo), float(dy_hi),
+                                _ptr(coef), _stream()), "md_spline_fit")
+    return coef
+
+
+class EAMPotential:
+    """Device B-spline coefficients of phi, rho, F and the packed interval tables."""
+
+    def __init__(self, c_phi, c_rho, c_emb, r_lo, r_h, e_lo, e_h, r_cut, device="cuda"):
+        dev = torch.device(device)
+        self.coef = [torch.as_tensor(np.asarray(c, np.float64) if not torch.is_tensor(c) else c,
+                                     dtype=torch.float64, device=dev).contiguous()
+                     for c in (c_phi, c_rho, c_emb)]
+        self.r_lo, self.r_h, self.e_lo, self.e_h = float(r_lo), float(r_h), float(e_lo), float(e_h)
+        self.r_cut = float(r_cut)
+        self.device = dev
+        self._tables = {}
+        self._build_struct()
+
+    def _build_struct(self):
+        cp, cr, ce = self.coef
+        self.c = N.EAM(N.Spline(cp.data_ptr(), cp.shape[0], 0, self.r_lo, self.r_h),
+                       N.Spline(cr.data_ptr(), cr.shape[0], 0, self.r_lo, self.r_h),
+                       N.Spline(ce.data_ptr(), ce.shape[0], 0, self.e_lo, self.e_h), self.r_cut)
+
+    @classmethod
+    def from_table(cls, table, device="cuda"):
+        """Fit a tabulated EAM (values on a grid plus end slopes) on the device."""
+        fits = [md_spline_fit(tf.y, tf.h, tf.dy_lo, tf.dy_hi, device)
+                for tf in (table.phi, table.rho, table.emb)]
+        if table.phi.x_lo != table.rho.x_lo or table.phi.h != table.rho.h:
+            raise ValueError("phi and rho must share one grid")
+        return cls(*fits, table.rho.x_lo, table.rho.h, table.emb.x_lo, table.emb.h, table.r_cut,
+                   device)
+
+    def set_coefficients(self, c_phi=None, c_rho=None, c_emb=None):
+        for k, c in enumerate((c_phi, c_rho, c_emb)):
+            if c is not None:
+                self.coef[k].copy_(torch.as_tensor(c, dtype=torch.float64))
+        self._tables = {}
+        self._build_struct()
+
+    def table(self, precision):
+        """Packed interval tables (md_eam_prepare), rebuilt after coefficient changes."""
+        if precision not in self._tables:
+            nbytes = int(N.lib().md_eam_table_bytes(C.byref(self.c), precision))
+            if nbytes == 0:
+                raise ValueError("invalid EAM description")
+            t = torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
+            self._tables[precision] = t
+        t = self._tables[precision]
+        check(N.lib().md_eam_prepare(C.byref(self.c), precision, _ptr(t), _stream()),
+              "md_eam_prepare")
+        return t
+
+
+def lj_params(eps, sigma, r_cut):
+    return N.LJ(float(eps), float(sigma), float(r_cut))
+
+
+def walls_params(walls):
+    if not walls:
+        return None
+    return N.Walls(1, int(walls["axis"]), float(walls["piston_z0"]), float(walls["piston_v"]),
+                   float(walls["top_z"]))
+
+
+# ----------------------------------------------------------------------------
+# The C entry points
+# ----------------------------------------------------------------------------
+def md_bin_cells(st: State, mode=N.MD_ALWAYS, stream=None):
+    check(N.lib().md_bin_cells(C.byref(st.plan.c), mode, _ptr(st.pos), _ptr(st.vel), _ptr(st.id),
+                               _ptr(st.pos_ref), _ptr(st.cell_start), _ptr(st.ws), _ptr(st.ctl),
+                               _stream(stream)), "md_bin_cells")
+
+
+def md_build_neighbors(st: State, nl: NeighborList, mode=N.MD_ALWAYS, stream=None):
+    check(N.lib().md_build_neighbors(C.byref(st.plan.c), mode, _ptr(st.pos), _ptr(st.cell_start),
+                                     C.byref(nl.c), _ptr(st.ctl), _stream(stream)),
+          "md_build_neighbors")
+
+
+def md_lj_forces(st: State, p, nl: NeighborList, inv_mass=0.0, half_dt=0.0, kick=False,
+                 ev=None, ev_cap=1, stream=None):
+    vel = st.vel if kick else None
+    check(N.lib().md_lj_forces(C.byref(st.plan.c), C.byref(p), st.precision, _ptr(st.pos),
+                               C.byref(nl.c), _ptr(st.force), _ptr(vel), float(inv_mass),
+                               float(half_dt), _ptr(ev), int(ev_cap), _ptr(st.ws), _ptr(st.ctl),
+                               _stream(stream)), "md_lj_forces")
+
+
+def md_eam_forces(st: State, pot: EAMPotential, nl: NeighborList, table=None, saved=None,
+                  inv_mass=0.0, half_dt=0.0, kick=False, ev=None, ev_cap=1, stream=None):
+    table = pot.table(st.precision) if table is None else table
+    vel = st.vel if kick else None
+    check(N.lib().md_eam_forces(C.byref(st.plan.c), C.byref(pot.c), st.precision, _ptr(table),
+                                _ptr(st.pos), C.byref(nl.c), _ptr(st.force), _ptr(saved),
+                                _ptr(vel), float(inv_mass), float(half_dt), _ptr(ev), int(ev_cap),
+                                _ptr(st.ws), _ptr(st.ctl), _stream(stream)), "md_eam_forces")
+
+
+def md_verlet_step(st: State, phase, dt, inv_mass, walls=None, half_skin=-1.0, stream=None):
+    w = walls_params(walls) if isinstance(walls, dict) else walls
+    check(N.lib().md_verlet_step(C.byref(st.plan.c), phase, float(dt), _ptr(st.pos), _ptr(st.vel),
+                                 _ptr(st.force), st.precision, float(inv_mass),
+                                 C.byref(w) if w is not None else None, _ptr(st.pos_ref),
+                                 float(half_skin), _ptr(st.ctl), _stream(stream)),
+          "md_verlet_step")
+
+
+def md_eam_backward(st: State, pot: EAMPotential, nl: NeighborList, saved, grad_force, ws=None,
+                    stream=None):
+    """grad_force: [3, n] FP64 cotangent in the current atom order.  Returns [n_coef total]."""
+    L = N.lib()
+    nb = int(L.md_backward_workspace_bytes(C.byref(st.plan.c), C.byref(pot.c)))
+    if nb == 0:
+        raise ValueError("backward not available for this spline size")
+    if ws is None or ws.numel() < nb:
+        ws = torch.zeros(nb, dtype=torch.uint8, device=st.pos.device)
+    out = torch.zeros(sum(c.shape[0] for c in pot.coef), dtype=torch.float64, device=st.pos.device)
+    check(L.md_eam_backward(C.byref(st.plan.c), C.byref(pot.c), st.precision, _ptr(st.pos),
+                            C.byref(nl.c), _ptr(saved), _ptr(grad_force), _ptr(out), _ptr(ws),
+                            _ptr(st.ctl), _stream(stream)), "md_eam_backward")
+    return out

@@ -1,0 +1,101 @@
+"""NVE driver: the sequence of library calls that makes one velocity-Verlet step
+(Sec. 1.5) with predicated neighbour-list rebuilds (Sec. 1.4), optionally
+captured once into a HIP graph and replayed.
+
+One step, all on one stream, no host synchronisation:
+  md_verlet_step(KICK_DRIFT)          v += dt/2 f/m; x += dt v; walls; displacement check
+  md_bin_cells(IF_FLAGGED)            wrap + counting sort, only if an atom moved > skin/2
+  md_build_neighbors(IF_FLAGGED)      Verlet list, same predicate
+  md_eam_forces / md_lj_forces        forces, energy, virial, trailing kick v += dt/2 f/m
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _native as N
+from . import md
+
+
+class Simulation:
+    def __init__(self, system, precision=N.MD_FP64, lanes=4, max_neigh=128, ev_cap=1024,
+                 device="cuda", table=None):
+        self.sys = system
+        self.precision = precision
+        r_cut = system.lj.r_cut if system.potential == "lj" else system.eam.r_cut
+        self.r_ns = r_cut + system.skin
+        self.plan = md.Plan([system.box], [system.pos.shape[0]], self.r_ns, device)
+        self.state = md.State(self.plan, system.pos, system.vel, precision)
+        self.nl = md.NeighborList(self.plan.n_atoms, max_neigh, lanes, device)
+        self.inv_mass = 1.0 / system.mass
+        self.dt = system.dt_ps
+        self.half_skin = 0.5 * system.skin
+        self.walls = md.walls_params(system.walls)
+        self.ev_cap = ev_cap
+        self.ev = torch.zeros((ev_cap, 1, N.MD_EV_LEN), dtype=torch.float64, device=device)
+        if system.potential == "lj":
+            self.lj = md.lj_params(system.lj.eps, system.lj.sigma, system.lj.r_cut)
+            self.pot = None
+        else:
+            self.pot = md.EAMPotential.from_table(table or system.table, device)
+            self.table = self.pot.table(precision)
+        self.graph = None
+        self.graph_steps = 0
+
+    # -- pieces ---------------------------------------------------------------
+    def forces(self, kick, ev=True):
+        st = self.state
+        half_dt = 0.5 * self.dt if kick else 0.0
+        evb = self.ev if ev else None
+        if self.pot is None:
+            md.md_lj_forces(st, self.lj, self.nl, self.inv_mass, half_dt, kick=True, ev=evb,
+                            ev_cap=self.ev_cap)
+        else:
+            md.md_eam_forces(st, self.pot, self.nl, self.table, None, self.inv_mass, half_dt,
+                             kick=True, ev=evb, ev_cap=self.ev_cap)
+
+    def setup(self):
+        """Initial binning, list and forces (step 0: energies with the initial velocities)."""
+        md.md_bin_cells(self.state, N.MD_ALWAYS)
+        md.md_build_neighbors(self.state, self.nl, N.MD_ALWAYS)
+        self.forces(kick=False)
+        return self
+
+    def step(self, ev=True):
+        st = self.state
+        md.md_verlet_step(st, N.MD_KICK_DRIFT, self.dt, self.inv_mass, self.walls, self.half_skin)
+        md.md_bin_cells(st, N.MD_IF_FLAGGED)
+        md.md_build_neighbors(st, self.nl, N.MD_IF_FLAGGED)
+        self.forces(kick=True, ev=ev)
+
+    # -- graphs ---------------------------------------------------------------
+    def capture(self, steps, ev=True):
+        """Capture `steps` consecutive steps into one graph."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(steps):
+                self.step(ev)
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph, self.graph_steps = g, steps
+        return g
+
+    def run(self, n_steps, graph_steps=0, ev=True):
+        if graph_steps and n_steps >= graph_steps:
+            if self.graph is None or self.graph_steps != graph_steps:
+                self.capture(graph_steps, ev)
+            for _ in range(n_steps // graph_steps):
+                self.graph.replay()
+            rest = n_steps % graph_steps
+        else:
+            rest = n_steps
+        for _ in range(rest):
+            self.step(ev)
+
+    # -- results --------------------------------------------------------------
+    def energies(self, steps):
+        """(step, PE, KE, W[6]) for the given step numbers (must be within the last ev_cap)."""
+        ev = self.ev.cpu().numpy()[:, 0, :]
+        rows = [ev[s % self.ev_cap] for s in steps]
+        return np.array(rows)

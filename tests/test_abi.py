@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every symbol include/md.h declares; host-only
+entry points (planning, sizes, status strings) work without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "md.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2511_22951_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        pytest.fail("libmd950.so not built; run __graft_entry__.build()")
+    return _native.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 18
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    from paper_2511_22951_amd import _native
+    assert set(names) == set(_native.EXPORTED)
+
+
+def test_plan_on_host(lib):
+    from paper_2511_22951_amd import _native as N
+    import mdinputs as mi
+    pos, box = mi.fcc_lattice(32, 32, 32, 3.615)
+    b = (N.Box * 1)()
+    for a in range(3):
+        b[0].lo[a], b[0].len[a], b[0].periodic[a] = 0.0, box.len[a], 1
+    off = (C.c_int * 2)(0, len(pos))
+    nc, nt = C.c_int(), C.c_int()
+    assert lib.md_plan_count(1, b, off, 5.8, 64, C.byref(nc), C.byref(nt)) == 0
+    assert nc.value == 19 ** 3 and nt.value == len(pos) // 64
+    doms = (N.Domain * 1)()
+    tiles = (N.Tile * nt.value)()
+    assert lib.md_plan(1, b, off, 5.8, 64, doms, tiles) == 0
+    assert tuple(doms[0].nc) == (19, 19, 19)
+    assert tiles[nt.value - 1].first == len(pos) - 64 and tiles[5].count == 64
+
+
+def test_plan_rejects_small_box_and_bad_args(lib):
+    from paper_2511_22951_amd import _native as N
+    b = (N.Box * 1)()
+    for a in range(3):
+        b[0].len[a], b[0].periodic[a] = 11.0, 1
+    off = (C.c_int * 2)(0, 100)
+    nc, nt = C.c_int(), C.c_int()
+    assert lib.md_plan_count(1, b, off, 5.8, 64, C.byref(nc), C.byref(nt)) == -2  # MD_ERR_BOX
+    assert lib.md_plan_count(1, b, off, 5.0, 32, C.byref(nc), C.byref(nt)) == -1  # tile size
+    b[0].periodic[0] = 0  # a non-periodic axis does not need L > 2 r_ns
+    b[0].periodic[1] = 0
+    b[0].periodic[2] = 0
+    assert lib.md_plan_count(1, b, off, 5.8, 64, C.byref(nc), C.byref(nt)) == 0
+    assert lib.md_status_string(-3).decode().startswith("neighbour list overflow")
+
+
+def test_batch_plan_tiles_never_straddle_boxes(lib):
+    from paper_2511_22951_amd import _native as N
+    import mdinputs as mi
+    reps = mi.cold_curve_replicas()
+    n = len(reps)
+    b = (N.Box * n)()
+    offs = [0]
+    for r, rep in enumerate(reps):
+        for a in range(3):
+            b[r].len[a], b[r].periodic[a] = rep.box.len[a], 1
+        offs.append(offs[-1] + len(rep.pos))
+    off = (C.c_int * (n + 1))(*offs)
+    nc, nt = C.c_int(), C.c_int()
+    assert lib.md_plan_count(n, b, off, 5.8, 64, C.byref(nc), C.byref(nt)) == 0
+    doms = (N.Domain * n)()
+    tiles = (N.Tile * nt.value)()
+    assert lib.md_plan(n, b, off, 5.8, 64, doms, tiles) == 0
+    for t in range(nt.value):
+        T = tiles[t]
+        d = doms[T.rep]
+        assert d.atom_off <= T.first and T.first + T.count <= d.atom_off + d.n_atoms
+    assert sum(doms[r].n_tiles for r in range(n)) == nt.value

@@ -1,0 +1,229 @@
+"""GPU parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances:
+  neighbour sets, wrapped positions, cell order       bit-exact
+  FP64 forces / energy / virial                       relative 1e-12 (Frobenius) / 1e-12 / 1e-11
+  FP32 forces                                         relative 1e-5 (Frobenius, all atoms)
+  FP32 energy                                         1e-6 eV per atom
+"""
+import numpy as np
+import pytest
+import torch
+
+import mdinputs as mi
+from oracle import core, integrate
+from oracle import spline as osp
+from tests.gpu_util import assert_same_sets, displaced, neighbor_sets_by_id, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mdmod():
+    from paper_2511_22951_amd import md, _native
+    _native.lib()
+    return md
+
+
+def _setup(md, pos, box, r_ns, lanes=4, max_neigh=128, prec=0, vel=None):
+    plan = md.Plan([box], [len(pos)], r_ns)
+    st = md.State(plan, pos, vel, prec)
+    nl = md.NeighborList(len(pos), max_neigh, lanes)
+    md.md_bin_cells(st)
+    md.md_build_neighbors(st, nl)
+    return plan, st, nl
+
+
+# ----------------------------------------------------------------------------
+# splines
+# ----------------------------------------------------------------------------
+def test_spline_fit_matches_oracle(mdmod):
+    for tf in (mi.tabulate_eam(mi.EAM_CU).phi, mi.tabulate_eam(mi.EAM_CU).emb,
+               mi.force_matching_tables().rho):
+        got = mdmod.md_spline_fit(tf.y, tf.h, tf.dy_lo, tf.dy_hi).cpu().numpy()
+        want = osp.fit_table(tf)
+        assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+# ----------------------------------------------------------------------------
+# binning and neighbour lists
+# ----------------------------------------------------------------------------
+CASES = [
+    # name, cells, a, sigma, r_ns, periodic
+    ("lj_argon_256", 4, 5.26, 0.15, 2.5 * 3.405 + 0.3, (1, 1, 1)),
+    ("cu_864_ragged", 6, 3.615, 0.08, 5.8, (1, 1, 1)),
+    ("cu_tiny_grid_2cells", 4, 3.30, 0.05, 5.8, (1, 1, 1)),
+    ("cu_walled_z", 6, 3.615, 0.05, 5.8, (1, 1, 0)),
+]
+
+
+@pytest.mark.parametrize("name,cells,a,sigma,r_ns,per", CASES)
+@pytest.mark.parametrize("lanes", [1, 4, 16])
+def test_neighbor_sets_bit_exact(mdmod, name, cells, a, sigma, r_ns, per, lanes):
+    print("case", name, "lanes", lanes, flush=True)
+    pos, box = displaced(cells, a, sigma, seed=100 + cells, box_periodic=per)
+    if not per[2]:
+        pos[:, 2] = np.clip(pos[:, 2], 0.01, box.len[2] - 0.01)
+    assert core.min_gap(pos, box, r_ns) > 1e-9
+    plan, st, nl = _setup(mdmod, pos, box, r_ns, lanes=lanes)
+    info = st.check_flags()
+    cnt, want = core.neighbor_sets(pos, box, r_ns)
+    assert info["max_nneigh"] == cnt.max()
+    assert_same_sets(neighbor_sets_by_id(st, nl), want)
+    # wrapped positions equal the oracle's wrap bit for bit, and atoms are in cell order
+    assert np.array_equal(st.positions(), core.wrap(pos, box))
+    cs = st.cell_start.cpu().numpy()
+    assert cs[0] == 0 and cs[-1] == len(pos) and np.all(np.diff(cs) >= 0)
+
+
+def test_binning_wraps_far_outside_positions(mdmod):
+    pos, box = displaced(5, 3.615, 0.05, seed=7)
+    shift = np.random.default_rng(3).integers(-2, 3, pos.shape) * np.array(box.len)
+    x = pos + shift
+    plan, st, nl = _setup(mdmod, x, box, 5.8)
+    xw = core.wrap(x, box)
+    assert np.array_equal(st.positions(), xw)
+    cnt, want = core.neighbor_sets(xw, box, 5.8)
+    assert_same_sets(neighbor_sets_by_id(st, nl), want)
+
+
+def test_neighbor_overflow_is_reported(mdmod):
+    pos, box = displaced(4, 3.615, 0.05, seed=9)
+    plan, st, nl = _setup(mdmod, pos, box, 5.8, lanes=4, max_neigh=32)
+    with pytest.raises(mdmod.MDError) as e:
+        st.check_flags()
+    assert e.value.status == -3
+    st.clear_flags()
+    assert st.read_flags()[0] == 0
+
+
+# ----------------------------------------------------------------------------
+# forces
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("cells,lanes", [(4, 4), (5, 1), (5, 8)])
+def test_lj_fp64_matches_oracle(mdmod, cells, lanes):
+    p = mi.LJ_AR
+    pos, box = displaced(cells, 5.26, 0.15, seed=11)
+    plan, st, nl = _setup(mdmod, pos, box, p.r_cut + 0.3, lanes=lanes)
+    ev = torch.zeros((1, 1, 8), dtype=torch.float64, device="cuda")
+    mdmod.md_lj_forces(st, mdmod.lj_params(p.eps, p.sigma, p.r_cut), nl, ev=ev)
+    r = core.lj(pos, box, p.eps, p.sigma, p.r_cut)
+    assert rel_fro(st.forces(), r.force) < 1e-12
+    e = ev.cpu().numpy()[0, 0]
+    assert abs(e[0] - r.energy) < 1e-12 * abs(r.energy)
+    assert np.max(np.abs(e[1:7] - r.virial)) < 1e-11 * np.max(np.abs(r.virial))
+
+
+def test_lj_fp32_within_tolerance(mdmod):
+    p = mi.LJ_AR
+    pos, box = displaced(5, 5.26, 0.15, seed=12)
+    plan, st, nl = _setup(mdmod, pos, box, p.r_cut + 0.3, prec=1)
+    ev = torch.zeros((1, 1, 8), dtype=torch.float64, device="cuda")
+    mdmod.md_lj_forces(st, mdmod.lj_params(p.eps, p.sigma, p.r_cut), nl, ev=ev)
+    r = core.lj(pos, box, p.eps, p.sigma, p.r_cut)
+    assert rel_fro(st.forces(), r.force) < 1e-5
+    assert abs(ev.cpu().numpy()[0, 0, 0] - r.energy) / len(pos) < 1e-6
+
+
+@pytest.mark.parametrize("prec,lanes", [(0, 4), (0, 1), (0, 16), (1, 4), (1, 8)])
+def test_eam_matches_oracle(mdmod, prec, lanes):
+    tab = mi.tabulate_eam(mi.EAM_CU)
+    pos, box = displaced(6, 3.615, 0.08, seed=13)
+    plan, st, nl = _setup(mdmod, pos, box, 5.8, lanes=lanes, prec=prec)
+    pot = mdmod.EAMPotential.from_table(tab)
+    ev = torch.zeros((1, 1, 8), dtype=torch.float64, device="cuda")
+    saved = torch.zeros((3, len(pos)), dtype=torch.float64, device="cuda")
+    mdmod.md_eam_forces(st, pot, nl, saved=saved, ev=ev)
+    st.check_flags()
+    r = core.eam(pos, box, core.EAMPotential.from_table(tab))
+    e = ev.cpu().numpy()[0, 0]
+    order = st._order()
+    rb = saved.cpu().numpy()[0][order]
+    if prec == 0:
+        assert rel_fro(st.forces(), r.force) < 1e-12
+        assert abs(e[0] - r.energy) < 1e-12 * abs(r.energy)
+        assert np.max(np.abs(e[1:7] - r.virial)) < 1e-11 * np.max(np.abs(r.virial))
+        assert np.max(np.abs(rb - r.rhobar)) < 1e-12 * np.max(r.rhobar)
+    else:
+        assert rel_fro(st.forces(), r.force) < 1e-5
+        assert abs(e[0] - r.energy) / len(pos) < 1e-6
+        assert np.max(np.abs(rb - r.rhobar)) < 1e-5 * np.max(r.rhobar)
+
+
+def test_eam_table_range_flag(mdmod):
+    """Atoms pushed closer than the table start set MD_FLAG_TABLE_RANGE."""
+    tab = mi.tabulate_eam(mi.EAM_CU, r_lo=2.4)
+    pos, box = displaced(5, 3.615, 0.0, seed=1)
+    pos[1] = pos[0] + np.array([2.0, 0.0, 0.0])
+    plan, st, nl = _setup(mdmod, pos, box, 5.8)
+    mdmod.md_eam_forces(st, mdmod.EAMPotential.from_table(tab), nl)
+    with pytest.raises(mdmod.MDError) as e:
+        st.check_flags()
+    assert e.value.status == -4
+
+
+# ----------------------------------------------------------------------------
+# integration
+# ----------------------------------------------------------------------------
+def test_lj_argon_trajectory_100_steps(mdmod):
+    """LJ argon 256 atoms, 100 velocity-Verlet steps, FP64: positions, velocities and
+    energies follow the oracle."""
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.lj_argon()
+    sim = Simulation(s, precision=0, lanes=4).setup()
+    sim.run(100)
+    info = sim.state.check_flags()
+    assert info["step"] == 100 and info["n_rebuilds"] >= 2
+    fn = integrate.lj_force_fn(s.box, s.lj)
+    x, v, f, hist = integrate.run_nve(s.pos, s.vel, s.box, s.mass, s.dt_ps, 100, fn)
+    d = sim.state.positions() - x
+    L = np.array(s.box.len)
+    d -= L * np.rint(d / L)
+    assert np.max(np.abs(d)) < 1e-9
+    assert np.max(np.abs(sim.state.velocities() - v)) < 1e-8
+    e = sim.energies(range(101))
+    assert np.max(np.abs(e[:, 0] - hist[:, 1])) < 1e-10 * abs(hist[0, 1])
+    assert np.max(np.abs(e[:, 7] - hist[:, 2])) < 1e-10 * abs(hist[0, 2])
+
+
+def test_eam_cu_trajectory_20_steps_and_graph_replay(mdmod):
+    """EAM Cu 864 atoms: 20 eager steps follow the oracle; a graph-captured run replays
+    the same trajectory bit for bit."""
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.eam_copper(cells=6)
+    sim = Simulation(s, precision=0, lanes=4).setup()
+    sim.run(20)
+    sim.state.check_flags()
+    pot = core.EAMPotential.from_table(s.table)
+    x, v, f, hist = integrate.run_nve(s.pos, s.vel, s.box, s.mass, s.dt_ps, 20,
+                                      integrate.eam_force_fn(s.box, pot))
+    d = sim.state.positions() - x
+    L = np.array(s.box.len)
+    d -= L * np.rint(d / L)
+    assert np.max(np.abs(d)) < 1e-9
+    e = sim.energies(range(21))
+    assert np.max(np.abs(e[:, 0] - hist[:, 1])) < 1e-10 * abs(hist[0, 1])
+    g = Simulation(s, precision=0, lanes=4).setup()
+    g.run(20, graph_steps=10)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.state.positions(), sim.state.positions())
+    assert np.array_equal(g.energies(range(21)), e)
+
+
+def test_piston_walls_match_oracle(mdmod):
+    """Walled box (periodic x, y; piston and top wall on z), 30 steps; a 10 km/s piston so
+    that atoms are reflected within the run."""
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.eam_aluminum_shock(nx=4, ny=4, nz=8)
+    s.walls = dict(s.walls, piston_v=100.0)
+    sim = Simulation(s, precision=0, lanes=4).setup()
+    sim.run(30)
+    sim.state.check_flags()
+    pot = core.EAMPotential.from_table(s.table)
+    x, v, f, hist = integrate.run_nve(s.pos, s.vel, s.box, s.mass, s.dt_ps, 30,
+                                      integrate.eam_force_fn(s.box, pot), walls=s.walls)
+    d = sim.state.positions() - x
+    L = np.array(s.box.len)
+    per = np.array(s.box.periodic, bool)
+    d[:, per] -= L[per] * np.rint(d[:, per] / L[per])
+    assert np.max(np.abs(d)) < 1e-9
