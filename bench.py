@@ -1,0 +1,224 @@
+"""Benchmark: EAM copper NVE throughput (atom-steps/s) on one MI355X.
+
+Workload: EAM Cu, fcc 32^3 cells = 131,072 atoms, a = 3.615 A, N(0, 0.05^2) A
+displacements, 300 K velocities, dt = 1 fs, skin 0.3 A (r_ns = 5.8 A), 2000-point
+spline tables; velocity Verlet with predicated neighbour-list rebuilds (half-skin
+displacement check), energies and virial reduced every step.  A step is the whole
+hot path: kick-drift + displacement check, (predicated) binning and list build,
+EAM density pass, EAM force pass with the trailing kick and reductions.
+
+Two GPU paths are timed: FP32-mixed (FP32 pair arithmetic and force sums, FP64
+positions/integration/reductions) -- the headline `value` -- and plain FP64.
+The timed region replays HIP graphs of `--graph-steps` steps; inputs are resident
+in HBM.  Kernel durations for the roofline are taken live with HIP events placed
+by the library around single launches (hipExtLaunchKernelGGL).
+
+`cpu_baseline` times the FP64 O(N^2) oracle (one full step of the same state) on
+the host cores; it is the only part of this script that touches the oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--graph-steps", type=int, default=50)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: autotune)")
+    ap.add_argument("--kernel-samples", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
+    return ap.parse_args()
+
+
+def algorithmic_force_bytes(n_atoms, mean_neigh, force_bytes):
+    """EAM force pass, per atom: list length 4 B + list 4 B/entry + own record (x, y, z,
+    F') 32 B + force write 3 * force_bytes + velocity read and write 48 B (fused kick).
+    Neighbour records are gathered from cache (counted in the traffic measurement)."""
+    return n_atoms * (4.0 + 4.0 * mean_neigh + 32.0 + 3.0 * force_bytes + 48.0)
+
+
+def time_kernel(md_native, kernel, run_once, samples):
+    """Mean duration (ms) of one kernel over `samples` launches, each inside run_once()."""
+    L = md_native.lib()
+    ms = C.c_float()
+    out = []
+    for _ in range(samples):
+        md_native.check(L.md_timer_arm(md_native.MD_KERNEL[kernel]), "md_timer_arm")
+        run_once()
+        md_native.check(L.md_timer_read(C.byref(ms)), "md_timer_read")
+        out.append(ms.value)
+    return float(np.mean(out)), float(np.std(out))
+
+
+def run_path(system, prec, lanes, args):
+    import torch
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+
+    cap = args.warmup + args.steps + args.kernel_samples + 8
+    sim = Simulation(system, precision=prec, lanes=lanes, ev_cap=cap).setup()
+    torch.cuda.synchronize()
+    f0 = sim.state.forces()
+    sim.run(args.warmup, graph_steps=args.graph_steps)
+    torch.cuda.synchronize()
+    st0 = sim.state.read_flags()[1]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    sim.run(args.steps, graph_steps=args.graph_steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    status, info = sim.state.read_flags()
+    N.check(status, "device flags after the timed run")
+    steps = list(range(st0["step"], info["step"] + 1))
+    ev = sim.energies(steps)
+    n = system.pos.shape[0]
+    etot = (ev[:, 0] + ev[:, 7]) / n
+    tps = np.array(steps) * system.dt_ps
+    slope = float(np.polyfit(tps - tps[0], etot, 1)[0])
+    # live kernel timing of the EAM passes and the kick-drift kernel
+    kt = {}
+    for k in ("eam_force", "eam_density", "kick_drift"):
+        kt[k] = time_kernel(N, k, lambda: sim.step(), args.kernel_samples)
+    nneigh = sim.nl.nneigh[:n].double().mean().item()
+    torch.cuda.synchronize()
+    return {
+        "ms": ms, "steps": args.steps, "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"],
+        "drift_ev_per_atom_ps": slope, "e0_per_atom": float(etot[0]),
+        "energy_span_per_atom": float(np.max(etot) - np.min(etot)),
+        "kernels_ms": kt, "mean_neigh": nneigh, "max_nneigh": info["max_nneigh"], "f0": f0,
+        "lanes": lanes,
+    }
+
+
+def autotune_lanes(system, prec):
+    """Time the EAM force and density kernels for each lanes-per-atom option and keep the
+    fastest pair (project autotuner; see paper_2511_22951_amd/tune.py)."""
+    from paper_2511_22951_amd import tune
+    return tune.best_lanes(system, prec)
+
+
+def cpu_baseline(system, f_gpu):
+    """FP64 O(N^2) oracle: one full step (density pass, force pass, velocity Verlet) of the
+    same initial state, on all host threads.  Also returns the GPU step-0 force errors."""
+    from oracle import core, integrate
+    pot = core.EAMPotential.from_table(system.table)
+    x = core.wrap(system.pos, system.box)
+    t0 = time.perf_counter()
+    r = core.eam(x, system.box, pot)
+    v = system.vel + 0.5 * system.dt_ps * r.force / system.mass * integrate.ACCEL
+    x = x + system.dt_ps * v
+    dt = time.perf_counter() - t0
+    n = x.shape[0]
+    errs = {k: float(np.linalg.norm(f - r.force) / np.linalg.norm(r.force))
+            for k, f in f_gpu.items()}
+    return {"value": n / dt, "unit": "atom-steps/s", "cores": core.num_threads(),
+            "kind": "oracle",
+            "sample": "one full FP64 O(N^2) step (density + force + Verlet) of all %d atoms, "
+                      "%.1f s" % (n, dt)}, errs, float(r.energy / n)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build targets one GPU; --gpus %d is not supported (run with "
+              "--gpus 1)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import mdinputs as mi
+    from paper_2511_22951_amd import _native as N
+
+    N.lib()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    system = mi.eam_copper(cells=32)
+    n = system.pos.shape[0]
+    results = {}
+    precs = {"both": [("fp32", N.MD_FP32), ("fp64", N.MD_FP64)], "fp32": [("fp32", N.MD_FP32)],
+             "fp64": [("fp64", N.MD_FP64)]}[args.precision]
+    for name, prec in precs:
+        lanes = args.lanes or autotune_lanes(system, prec)
+        results[name] = run_path(system, prec, lanes, args)
+        print("[bench] %s: %.3f ms/step, lanes %d, force kernel %.2f us" % (
+            name, results[name]["ms"] / args.steps, lanes,
+            1e3 * results[name]["kernels_ms"]["eam_force"][0]), file=sys.stderr, flush=True)
+
+    head = "fp32" if "fp32" in results else "fp64"
+    R = results[head]
+    ms_step = R["ms"] / args.steps
+    value = n * args.steps / (R["ms"] * 1e-3)
+    fb = 4 if head == "fp32" else 8
+    kt_force = R["kernels_ms"]["eam_force"][0] * 1e-3
+    bytes_force = algorithmic_force_bytes(n, R["mean_neigh"], fb)
+    achieved = bytes_force / kt_force / 1e9
+
+    f_gpu = {k: r["f0"] for k, r in results.items()}
+    if args.no_cpu_baseline:
+        cpu, ferr, e_or = None, {}, None
+    else:
+        cpu, ferr, e_or = cpu_baseline(system, f_gpu)
+
+    out = {
+        "metric": "atom-steps/s (EAM Cu force+Verlet) FP32 vs FP64 at stated force error",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "EAM Cu fcc 32^3 = 131072 atoms, a 3.615, 300 K, dt 1 fs, "
+                               "skin 0.3, 2000-point splines, NVE velocity Verlet",
+                   "n_atoms": n, "precision": head, "lanes_per_atom": R["lanes"],
+                   "graph_steps": args.graph_steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_eam_force", "kernel_us": kt_force * 1e6,
+                     "bytes_per_launch": bytes_force},
+        "cpu_baseline": cpu,
+    }
+    paths = {}
+    for k, r in results.items():
+        paths[k] = {"atom_steps_per_s": n * args.steps / (r["ms"] * 1e-3),
+                    "ms_per_step": r["ms"] / args.steps, "lanes": r["lanes"],
+                    "rebuilds": r["rebuilds"], "mean_neigh": r["mean_neigh"],
+                    "nve_drift_eV_per_atom_ps": r["drift_ev_per_atom_ps"],
+                    "energy_span_eV_per_atom": r["energy_span_per_atom"],
+                    "kernel_us": {kk: 1e3 * v[0] for kk, v in r["kernels_ms"].items()},
+                    "force_rel_err_vs_oracle": ferr.get(k)}
+    if "fp32" in results and "fp64" in results:
+        paths["fp32"]["force_rel_err_vs_fp64_gpu"] = float(
+            np.linalg.norm(results["fp32"]["f0"] - results["fp64"]["f0"])
+            / np.linalg.norm(results["fp64"]["f0"]))
+        paths["speedup_fp32_over_fp64"] = results["fp64"]["ms"] / results["fp32"]["ms"]
+    if e_or is not None:
+        paths["oracle_e0_per_atom"] = e_or
+    out["paths"] = paths
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -271,6 +271,21 @@ int md_read_flags(const void* ctl, int* host_out, void* stream);
 /* Clear the sticky error flags (not the counters). */
 int md_clear_flags(void* ctl, void* stream);
 
+/* Kernel timing for measurement harnesses.  md_timer_arm(kernel) makes the next
+ * launch of that kernel (on any stream, by this host thread) record a start and a
+ * stop event around its execution (hipExtLaunchKernelGGL); md_timer_read waits for
+ * the stop event and returns the kernel's duration in milliseconds.  Library-owned
+ * events are created on first use.  Not for use under stream capture. */
+#define MD_KERNEL_BIN_COUNT 1
+#define MD_KERNEL_BUILD 2
+#define MD_KERNEL_LJ 3
+#define MD_KERNEL_EAM_DENSITY 4
+#define MD_KERNEL_EAM_FORCE 5
+#define MD_KERNEL_KICK_DRIFT 6
+#define MD_KERNEL_EAM_ADJOINT 7
+int md_timer_arm(int kernel);
+int md_timer_read(float* ms);
+
 /* Human-readable name of a status code (static string). */
 const char* md_status_string(int status);
 

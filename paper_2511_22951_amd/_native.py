@@ -94,7 +94,12 @@ _SIGS = {
     "md_read_flags": (_i, [_vp, _P(C.c_int), _vp]),
     "md_clear_flags": (_i, [_vp, _vp]),
     "md_status_string": (C.c_char_p, [_i]),
+    "md_timer_arm": (_i, [_i]),
+    "md_timer_read": (_i, [_P(C.c_float)]),
 }
+
+MD_KERNEL = {"bin_count": 1, "build": 2, "lj": 3, "eam_density": 4, "eam_force": 5,
+             "kick_drift": 6, "eam_adjoint": 7}
 
 EXPORTED = tuple(_SIGS)
 

@@ -209,9 +209,9 @@ extern "C" int md_eam_backward(const md_batch* b, const md_eam* p, md_precision 
     const size_t lds = (size_t)(64 * L / MD_WAVE) * g.n_bins * sizeof(double);
     if (lds > 65536) return MD_ERR_ARG;  // fewer lanes per atom, or fewer coefficients
 #define MD_ADJ_LAUNCH(LN)                                                                      \
-  hipLaunchKernelGGL(k_eam_adjoint<LN>, grid, block, lds, st, *b, (const double4*)pos,        \
-                     nl->neigh, nl->nneigh, npad, saved, grad_force, g, rc2, tile_bins,       \
-                     (md_ctl_dev*)ctl)
+  MD_LAUNCH_TIMED(MD_KERNEL_EAM_ADJOINT, k_eam_adjoint<LN>, grid, block, lds, st, *b,          \
+                  (const double4*)pos, nl->neigh, nl->nneigh, npad, saved, grad_force, g, rc2, \
+                  tile_bins, (md_ctl_dev*)ctl)
     switch (L) {
       case 1: MD_ADJ_LAUNCH(1); break;
       case 2: MD_ADJ_LAUNCH(2); break;

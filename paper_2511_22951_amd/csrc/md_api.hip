@@ -7,6 +7,43 @@
 
 int md_hip_status(hipError_t e) { return e == hipSuccess ? MD_OK : MD_ERR_HIP; }
 
+namespace {
+struct TimerSlot {
+  int armed = 0;
+  int pending = 0;
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+thread_local TimerSlot g_timer;
+}  // namespace
+
+bool md_timer_take(int kernel, hipEvent_t* start, hipEvent_t* stop) {
+  if (g_timer.armed == 0 || g_timer.armed != kernel) return false;
+  g_timer.armed = 0;
+  g_timer.pending = 1;
+  *start = g_timer.start;
+  *stop = g_timer.stop;
+  return true;
+}
+
+extern "C" int md_timer_arm(int kernel) {
+  if (kernel < MD_KERNEL_BIN_COUNT || kernel > MD_KERNEL_EAM_ADJOINT) return MD_ERR_ARG;
+  if (!g_timer.start) {
+    if (hipEventCreate(&g_timer.start) != hipSuccess) return MD_ERR_HIP;
+    if (hipEventCreate(&g_timer.stop) != hipSuccess) return MD_ERR_HIP;
+  }
+  g_timer.armed = kernel;
+  g_timer.pending = 0;
+  return MD_OK;
+}
+
+extern "C" int md_timer_read(float* ms) {
+  if (!ms || !g_timer.pending) return MD_ERR_ARG;
+  if (hipEventSynchronize(g_timer.stop) != hipSuccess) return MD_ERR_HIP;
+  if (hipEventElapsedTime(ms, g_timer.start, g_timer.stop) != hipSuccess) return MD_ERR_HIP;
+  g_timer.pending = 0;
+  return MD_OK;
+}
+
 static int plan_box(const md_box* bx, double r_ns, int nc[3]) {
   for (int a = 0; a < 3; ++a) {
     const double L = bx->len[a];
@@ -85,15 +122,15 @@ extern "C" size_t md_ctl_bytes(void) { return md_align256(sizeof(md_ctl_dev)); }
 
 __global__ void k_ctl_init(md_ctl_dev* ctl) {
   if (threadIdx.x == 0) {
-    ctl->dmax_bits = 0ull;
     ctl->rebuild = 0;
     ctl->step = 0;
     ctl->flags = 0;
     ctl->n_rebuilds = 0;
     ctl->max_nneigh = 0;
-    ctl->pad = 0;
-    for (int k = 0; k < 8; ++k) ctl->done[k] = 0u;
+    ctl->n_dmax = 0;
+    ctl->pad[0] = ctl->pad[1] = 0;
   }
+  for (int k = threadIdx.x; k < MD_MAX_ATOM_BLOCKS; k += blockDim.x) ctl->dmax[k] = 0.0;
 }
 
 __global__ void k_ctl_clear_flags(md_ctl_dev* ctl) {
@@ -102,7 +139,7 @@ __global__ void k_ctl_clear_flags(md_ctl_dev* ctl) {
 
 extern "C" int md_ctl_init(void* ctl, void* stream) {
   if (!ctl) return MD_ERR_ARG;
-  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, (hipStream_t)stream, (md_ctl_dev*)ctl);
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(256), 0, (hipStream_t)stream, (md_ctl_dev*)ctl);
   MD_LAUNCH_CHECK();
   return MD_OK;
 }

@@ -77,9 +77,11 @@ __device__ __forceinline__ double4 load_xyz(const double4* pos, int j) {
   return make_double4(a.x, a.y, c, 0.0);
 }
 
-// Final per-box reduction of the tile partials in fixed order (last block only).
-__device__ void reduce_partials(const md_batch& b, const double* partial, double* ev, int ev_cap,
-                                md_ctl_dev* ctl, double* sh) {
+// One block: per-box sums of the tile partials in fixed order, written to
+// ev[(step % ev_cap) * n_rep + rep].
+__global__ __launch_bounds__(1024) void k_ev_reduce(md_batch b, const double* partial, double* ev,
+                                                    int ev_cap, const md_ctl_dev* ctl) {
+  __shared__ double sh[MD_EV_LEN * 16];
   const int step = ctl->step;
   double* out = ev + (size_t)(step % ev_cap) * b.n_rep * MD_EV_LEN;
   if (b.n_rep == 1) {
@@ -97,11 +99,11 @@ __device__ void reduce_partials(const md_batch& b, const double* partial, double
     const int lane = threadIdx.x & (MD_WAVE - 1), wid = threadIdx.x / MD_WAVE;
     const int nw = blockDim.x / MD_WAVE;
     for (int r = wid; r < b.n_rep; r += nw) {
-      const md_domain D = b.domains[r];
+      const int t0 = b.domains[r].tile_off, t1 = t0 + b.domains[r].n_tiles;
       double v[MD_EV_LEN];
 #pragma unroll
       for (int k = 0; k < MD_EV_LEN; ++k) v[k] = 0.0;
-      for (int t = D.tile_off + lane; t < D.tile_off + D.n_tiles; t += MD_WAVE)
+      for (int t = t0 + lane; t < t1; t += MD_WAVE)
 #pragma unroll
         for (int k = 0; k < MD_EV_LEN; ++k) v[k] += partial[(size_t)t * MD_EV_LEN + k];
 #pragma unroll
@@ -111,7 +113,6 @@ __device__ void reduce_partials(const md_batch& b, const double* partial, double
         for (int k = 0; k < MD_EV_LEN; ++k) out[(size_t)r * MD_EV_LEN + k] = v[k];
     }
   }
-  if (threadIdx.x == 0) ctl->done[MD_DONE_FORCE] = 0u;
 }
 
 // Epilogue shared by the LJ and EAM force kernels: write the force, apply the
@@ -144,9 +145,10 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_density(
     md_batch b, double4* pos, const int* __restrict__ neigh, const int* __restrict__ nneigh,
     int npad, const R* __restrict__ rtab, const R* __restrict__ etab, TabGeom g, R rc2,
     double* saved, double* partial, md_ctl_dev* ctl) {
+  constexpr int U = 4;  // neighbours in flight per lane
   __shared__ double sh[MD_EV_LEN * 16];
   const int t = md_remap_block(b.n_tiles);
-  if (t >= b.n_tiles) return;  // no block-wide reduction follows for padding blocks
+  if (t >= b.n_tiles) return;  // padding block: no block-wide work follows
   const md_tile T = b.tiles[t];
   const Img D(&b.domains[T.rep]);
   const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
@@ -160,9 +162,8 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_density(
     R rho = 0, phi = 0;
     const int* nb = neigh + (size_t)i * LANES + l;
     const size_t stride = (size_t)npad * LANES;
-    for (int m = l; m < nn; m += LANES, nb += stride) {
-      const int j = *nb;
-      const Sep d = separation(D, load_xyz(pos, j), pi);
+    auto pair = [&](double4 pj) {
+      const Sep d = separation(D, pj, pi);
       const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
       const R r2 = x * x + y * y + z * z;
       if (r2 < rc2) {
@@ -173,7 +174,20 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_density(
         rho += ((row[3] * tt + row[2]) * tt + row[1]) * tt + row[0];
         if (EV) phi += ((row[7] * tt + row[6]) * tt + row[5]) * tt + row[4];
       }
+    };
+    int m = l;
+    for (; m + (U - 1) * LANES < nn; m += U * LANES) {
+      int j[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) j[u] = nb[u * stride];
+      nb += U * stride;
+      double4 pj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pj[u] = load_xyz(pos, j[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) pair(pj[u]);
     }
+    for (; m < nn; m += LANES, nb += stride) pair(load_xyz(pos, *nb));
     rho = md_group_sum<LANES>(rho);
     if (EV) e_acc += 0.5 * (double)phi;
     if (l == 0) {
@@ -212,75 +226,84 @@ template <typename R, int LANES, bool EV>
 __global__ __launch_bounds__(64 * LANES) void k_eam_force(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab, TabGeom g, R rc2,
-    R* force, double* vel, double inv_mass, double half_dt, double* partial, double* ev,
-    int ev_cap, md_ctl_dev* ctl) {
+    R* force, double* vel, double inv_mass, double half_dt, double* partial, md_ctl_dev* ctl) {
+  constexpr int U = 4;  // neighbours in flight per lane
   __shared__ double sh[MD_EV_LEN * 16];
   const int t = md_remap_block(b.n_tiles);
-  const bool active = t < b.n_tiles;
+  if (t >= b.n_tiles) return;
+  const md_tile T = b.tiles[t];
+  const Img D(&b.domains[T.rep]);
+  const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // W xx yy zz xy xz yz, K
   bool oor = false;
-  if (active) {
-    const md_tile T = b.tiles[t];
-    const Img D(&b.domains[T.rep]);
-    const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
-    R fx = 0, fy = 0, fz = 0;
-    R w[6] = {0, 0, 0, 0, 0, 0};
-    int i = -1;
-    if (a < T.count) {
-      i = T.first + a;
-      const double4 pi = pos[i];
-      const R fpi = (R)pi.w;
-      const int nn = nneigh[i];
-      const R rlo = (R)g.r_lo, rih = (R)g.r_inv_h;
-      const int* nb = neigh + (size_t)i * LANES + l;
-      const size_t stride = (size_t)npad * LANES;
-      for (int m = l; m < nn; m += LANES, nb += stride) {
-        const int j = *nb;
-        const double4 pj = pos[j];
-        const Sep d = separation(D, pj, pi);
-        const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
-        const R r2 = x * x + y * y + z * z;
-        if (r2 < rc2) {
-          const R rinv = rsqrt_r<R>(r2);
-          const R r = r2 * rinv;
-          R tt;
-          const int k = tab_index<R>(r, rlo, rih, g.nr, tt, oor);
-          const R* row = ftab + (size_t)k * MD_FTAB_W;
-          const R dphi = (row[2] * tt + row[1]) * tt + row[0];
-          const R drho = (row[5] * tt + row[4]) * tt + row[3];
-          const R s = (dphi + (fpi + (R)pj.w) * drho) * rinv;
-          fx += s * x;
-          fy += s * y;
-          fz += s * z;
-          if (EV) {
-            w[0] -= s * x * x;
-            w[1] -= s * y * y;
-            w[2] -= s * z * z;
-            w[3] -= s * x * y;
-            w[4] -= s * x * z;
-            w[5] -= s * y * z;
-          }
+  R fx = 0, fy = 0, fz = 0;
+  R w[6] = {0, 0, 0, 0, 0, 0};
+  int i = -1;
+  if (a < T.count) {
+    i = T.first + a;
+    const double4 pi = pos[i];
+    const R fpi = (R)pi.w;
+    const int nn = nneigh[i];
+    const R rlo = (R)g.r_lo, rih = (R)g.r_inv_h;
+    const int* nb = neigh + (size_t)i * LANES + l;
+    const size_t stride = (size_t)npad * LANES;
+    auto pair = [&](double4 pj) {
+      const Sep d = separation(D, pj, pi);
+      const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
+      const R r2 = x * x + y * y + z * z;
+      if (r2 < rc2) {
+        const R rinv = rsqrt_r<R>(r2);
+        const R r = r2 * rinv;
+        R tt;
+        const int k = tab_index<R>(r, rlo, rih, g.nr, tt, oor);
+        const R* row = ftab + (size_t)k * MD_FTAB_W;
+        const R dphi = (row[2] * tt + row[1]) * tt + row[0];
+        const R drho = (row[5] * tt + row[4]) * tt + row[3];
+        // force on i from j: s (r_j - r_i), s = [phi' + (F'_i + F'_j) rho'] / r
+        const R s = (dphi + (fpi + (R)pj.w) * drho) * rinv;
+        fx += s * x;
+        fy += s * y;
+        fz += s * z;
+        if (EV) {
+          w[0] -= s * x * x;
+          w[1] -= s * y * y;
+          w[2] -= s * z * z;
+          w[3] -= s * x * y;
+          w[4] -= s * x * z;
+          w[5] -= s * y * z;
         }
       }
-    }
-    fx = md_group_sum<LANES>(fx);
-    fy = md_group_sum<LANES>(fy);
-    fz = md_group_sum<LANES>(fz);
-    if (i >= 0 && l == 0)
-      acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
-    if (EV)
+    };
+    int m = l;
+    for (; m + (U - 1) * LANES < nn; m += U * LANES) {
+      int j[U];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) acc[k] = 0.5 * (double)w[k];
+      for (int u = 0; u < U; ++u) j[u] = nb[u * stride];
+      nb += U * stride;
+      double4 pj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pj[u] = pos[j[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pair(pj[u]);
+    }
+    for (; m < nn; m += LANES, nb += stride) pair(pos[*nb]);
   }
+  fx = md_group_sum<LANES>(fx);
+  fy = md_group_sum<LANES>(fy);
+  fz = md_group_sum<LANES>(fz);
+  if (i >= 0 && l == 0)
+    acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
+  if (EV)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] = 0.5 * (double)w[k];
   if (__any(oor)) {
     if ((threadIdx.x & (MD_WAVE - 1)) == 0) md_flag(ctl, MD_FLAG_TABLE_RANGE);
   }
   if (EV) {
     md_block_sum<7>(acc, sh);
-    if (active && threadIdx.x == 0)
+    if (threadIdx.x == 0)
 #pragma unroll
       for (int k = 0; k < 7; ++k) partial[(size_t)t * MD_EV_LEN + 1 + k] = acc[k];
-    if (md_last_block(&ctl->done[MD_DONE_FORCE])) reduce_partials(b, partial, ev, ev_cap, ctl, sh);
   }
 }
 
@@ -295,69 +318,77 @@ template <typename R, int LANES, bool EV>
 __global__ __launch_bounds__(64 * LANES) void k_lj(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, LJc c, R rc2, R* force, double* vel,
-    double inv_mass, double half_dt, double* partial, double* ev, int ev_cap, md_ctl_dev* ctl) {
+    double inv_mass, double half_dt, double* partial, md_ctl_dev* ctl) {
+  constexpr int U = 4;
   __shared__ double sh[MD_EV_LEN * 16];
   const int t = md_remap_block(b.n_tiles);
-  const bool active = t < b.n_tiles;
+  if (t >= b.n_tiles) return;
+  const md_tile T = b.tiles[t];
+  const Img D(&b.domains[T.rep]);
+  const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // E, W xx yy zz xy xz yz, K
-  if (active) {
-    const md_tile T = b.tiles[t];
-    const Img D(&b.domains[T.rep]);
-    const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
-    const R sig2 = (R)c.sig2, eps4 = (R)c.eps4, eps24 = (R)c.eps24, ucut = (R)c.ucut;
-    R fx = 0, fy = 0, fz = 0, e = 0;
-    R w[6] = {0, 0, 0, 0, 0, 0};
-    int i = -1;
-    if (a < T.count) {
-      i = T.first + a;
-      const double4 pi = pos[i];
-      const int nn = nneigh[i];
-      const int* nb = neigh + (size_t)i * LANES + l;
-      const size_t stride = (size_t)npad * LANES;
-      for (int m = l; m < nn; m += LANES, nb += stride) {
-        const int j = *nb;
-        const Sep d = separation(D, pos[j], pi);
-        const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
-        const R r2 = x * x + y * y + z * z;
-        if (r2 < rc2) {
-          const R ir2 = (R)1 / r2;
-          const R sr2 = sig2 * ir2;
-          const R sr6 = sr2 * sr2 * sr2;
-          const R sr12 = sr6 * sr6;
-          // f_i = -dU/dr r_ij / r = -24 eps (2 sr12 - sr6) / r^2 (r_j - r_i)
-          const R s = -eps24 * ((R)2 * sr12 - sr6) * ir2;
-          fx += s * x;
-          fy += s * y;
-          fz += s * z;
-          if (EV) {
-            e += eps4 * (sr12 - sr6) - ucut;
-            w[0] -= s * x * x;
-            w[1] -= s * y * y;
-            w[2] -= s * z * z;
-            w[3] -= s * x * y;
-            w[4] -= s * x * z;
-            w[5] -= s * y * z;
-          }
+  const R sig2 = (R)c.sig2, eps4 = (R)c.eps4, eps24 = (R)c.eps24, ucut = (R)c.ucut;
+  R fx = 0, fy = 0, fz = 0, e = 0;
+  R w[6] = {0, 0, 0, 0, 0, 0};
+  int i = -1;
+  if (a < T.count) {
+    i = T.first + a;
+    const double4 pi = pos[i];
+    const int nn = nneigh[i];
+    const int* nb = neigh + (size_t)i * LANES + l;
+    const size_t stride = (size_t)npad * LANES;
+    auto pair = [&](double4 pj) {
+      const Sep d = separation(D, pj, pi);
+      const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
+      const R r2 = x * x + y * y + z * z;
+      if (r2 < rc2) {
+        const R ir2 = (R)1 / r2;
+        const R sr2 = sig2 * ir2;
+        const R sr6 = sr2 * sr2 * sr2;
+        const R sr12 = sr6 * sr6;
+        // f_i = -dU/dr r_ij / r = -24 eps (2 sr12 - sr6) / r^2 (r_j - r_i)
+        const R s = -eps24 * ((R)2 * sr12 - sr6) * ir2;
+        fx += s * x;
+        fy += s * y;
+        fz += s * z;
+        if (EV) {
+          e += eps4 * (sr12 - sr6) - ucut;
+          w[0] -= s * x * x;
+          w[1] -= s * y * y;
+          w[2] -= s * z * z;
+          w[3] -= s * x * y;
+          w[4] -= s * x * z;
+          w[5] -= s * y * z;
         }
       }
-    }
-    fx = md_group_sum<LANES>(fx);
-    fy = md_group_sum<LANES>(fy);
-    fz = md_group_sum<LANES>(fz);
-    if (i >= 0 && l == 0)
-      acc[7] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
-    if (EV) {
-      acc[0] = 0.5 * (double)e;
+    };
+    int m = l;
+    for (; m + (U - 1) * LANES < nn; m += U * LANES) {
+      int j[U];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) acc[1 + k] = 0.5 * (double)w[k];
+      for (int u = 0; u < U; ++u) j[u] = nb[u * stride];
+      nb += U * stride;
+      double4 pj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pj[u] = pos[j[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pair(pj[u]);
     }
+    for (; m < nn; m += LANES, nb += stride) pair(pos[*nb]);
   }
+  fx = md_group_sum<LANES>(fx);
+  fy = md_group_sum<LANES>(fy);
+  fz = md_group_sum<LANES>(fz);
+  if (i >= 0 && l == 0)
+    acc[7] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
   if (EV) {
+    acc[0] = 0.5 * (double)e;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[1 + k] = 0.5 * (double)w[k];
     md_block_sum<8>(acc, sh);
-    if (active && threadIdx.x == 0)
+    if (threadIdx.x == 0)
 #pragma unroll
       for (int k = 0; k < 8; ++k) partial[(size_t)t * MD_EV_LEN + k] = acc[k];
-    if (md_last_block(&ctl->done[MD_DONE_FORCE])) reduce_partials(b, partial, ev, ev_cap, ctl, sh);
   }
 }
 
@@ -395,17 +426,20 @@ void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_ta
   const R* ftab = (const R*)(tab + TL.ftab);
   const R* etab = (const R*)(tab + TL.etab);
   if (ev) {
-    hipLaunchKernelGGL((k_eam_density<R, LANES, true>), grid, block, 0, st, b, (double4*)pos,
-                       nl.neigh, nl.nneigh, npad, rtab, etab, g, rc2, saved, partial, ctl);
-    hipLaunchKernelGGL((k_eam_force<R, LANES, true>), grid, block, 0, st, b,
-                       (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g, rc2, (R*)force,
-                       vel, inv_mass, half_dt, partial, ev, ev_cap, ctl);
+    MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density<R, LANES, true>), grid, block, 0, st, b,
+                    (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g, rc2, saved, partial,
+                    ctl);
+    MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force<R, LANES, true>), grid, block, 0, st, b,
+                    (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g, rc2, (R*)force, vel,
+                    inv_mass, half_dt, partial, ctl);
+    hipLaunchKernelGGL(k_ev_reduce, dim3(1), dim3(1024), 0, st, b, partial, ev, ev_cap, ctl);
   } else {
-    hipLaunchKernelGGL((k_eam_density<R, LANES, false>), grid, block, 0, st, b, (double4*)pos,
-                       nl.neigh, nl.nneigh, npad, rtab, etab, g, rc2, saved, partial, ctl);
-    hipLaunchKernelGGL((k_eam_force<R, LANES, false>), grid, block, 0, st, b,
-                       (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g, rc2, (R*)force,
-                       vel, inv_mass, half_dt, partial, ev, ev_cap, ctl);
+    MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density<R, LANES, false>), grid, block, 0, st,
+                    b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g, rc2, saved,
+                    partial, ctl);
+    MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force<R, LANES, false>), grid, block, 0, st, b,
+                    (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g, rc2, (R*)force, vel,
+                    inv_mass, half_dt, partial, ctl);
   }
 }
 
@@ -422,14 +456,16 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
   const R rc2 = (R)(p.r_cut * p.r_cut);
   const dim3 grid(md_grid_blocks(b.n_tiles)), block(64 * LANES);
   const int npad = md_npad(b.n_atoms);
-  if (ev)
-    hipLaunchKernelGGL((k_lj<R, LANES, true>), grid, block, 0, st, b, (const double4*)pos,
-                       nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel, inv_mass, half_dt,
-                       partial, ev, ev_cap, ctl);
-  else
-    hipLaunchKernelGGL((k_lj<R, LANES, false>), grid, block, 0, st, b, (const double4*)pos,
-                       nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel, inv_mass, half_dt,
-                       partial, ev, ev_cap, ctl);
+  if (ev) {
+    MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, true>), grid, block, 0, st, b,
+                    (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,
+                    inv_mass, half_dt, partial, ctl);
+    hipLaunchKernelGGL(k_ev_reduce, dim3(1), dim3(1024), 0, st, b, partial, ev, ev_cap, ctl);
+  } else {
+    MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, false>), grid, block, 0, st, b,
+                    (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,
+                    inv_mass, half_dt, partial, ctl);
+  }
 }
 
 }  // namespace

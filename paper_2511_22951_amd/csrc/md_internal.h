@@ -1,6 +1,7 @@
 // Internal definitions shared by the HIP translation units of libmd950.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -16,17 +17,18 @@
 #define MD_ACCEL 9648.5332157
 
 // Device control block (md_ctl_bytes()).
+#define MD_MAX_ATOM_BLOCKS 4096  // grid cap of the per-atom kernels (grid-stride beyond)
+
 struct md_ctl_dev {
-  unsigned long long dmax_bits;  // max |x - x_ref|^2 of the running drift, as raw bits
-  int rebuild;                   // 1: the MD_IF_FLAGGED rebuild kernels do their work
-  int step;                      // completed kick-drift steps
-  int flags;                     // sticky MD_FLAG_* bits
+  int rebuild;     // 1: the MD_IF_FLAGGED rebuild kernels do their work
+  int step;        // completed kick-drift steps
+  int flags;       // sticky MD_FLAG_* bits
   int n_rebuilds;
   int max_nneigh;
-  int pad;
-  unsigned int done[8];          // arrival counters of the last-block reductions
+  int n_dmax;      // number of valid entries in dmax[]
+  int pad[2];
+  double dmax[MD_MAX_ATOM_BLOCKS];  // per-block max |x - x_ref|^2 of the last drift
 };
-enum { MD_DONE_BIN = 0, MD_DONE_VERLET = 1, MD_DONE_FORCE = 2, MD_DONE_ADJ = 3 };
 
 // Offsets of the workspace regions (bytes, 256-aligned).
 struct md_ws_layout {
@@ -55,6 +57,13 @@ static inline int md_npad(int n) { return (n + 63) & ~63; }
 // is a bijection.
 static inline int md_grid_blocks(int nblocks) { return ((nblocks + MD_XCD - 1) / MD_XCD) * MD_XCD; }
 
+// Per-atom kernels: 256-thread blocks of 4 tiles, at most MD_MAX_ATOM_BLOCKS blocks
+// (a block then strides over logical blocks).
+static inline int md_atom_grid(int n_tiles) {
+  const int g = md_grid_blocks((n_tiles + 3) / 4);
+  return g < MD_MAX_ATOM_BLOCKS ? g : MD_MAX_ATOM_BLOCKS;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
 // Give each XCD a contiguous range of logical blocks, so that spatially adjacent
 // tiles (cell order) share an L2.  Returns a value >= nblocks for padding blocks.
@@ -62,6 +71,15 @@ __device__ __forceinline__ int md_remap_block(int nblocks) {
   const int per = (nblocks + MD_XCD - 1) / MD_XCD;
   const int b = blockIdx.x;
   return (b % MD_XCD) * per + b / MD_XCD;
+}
+
+// Same remap for a grid of gridDim.x blocks striding over nblocks logical blocks:
+// the k-th logical block of block b.
+__device__ __forceinline__ int md_remap_stride(int nblocks, int k) {
+  const int g = gridDim.x;
+  const int per = (g + MD_XCD - 1) / MD_XCD;
+  const int b = blockIdx.x;
+  return ((b % MD_XCD) * per + b / MD_XCD) + k * g;
 }
 
 __device__ __forceinline__ void md_flag(md_ctl_dev* ctl, int bits) { atomicOr(&ctl->flags, bits); }
@@ -108,24 +126,26 @@ __device__ __forceinline__ void md_block_sum(double (&v)[NV], double* sh) {
   __syncthreads();
 }
 
-// Last-block detection: every block calls this once after its global writes.
-// Returns true in exactly one block, the last to arrive, after which every
-// write of every block is visible to it.  Never waits on other blocks.
-__device__ __forceinline__ bool md_last_block(unsigned int* counter) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int prev = atomicAdd(counter, 1u);
-    s_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last != 0;
-}
+// Cross-block results are never combined inside a kernel: on MI355X each of the
+// 8 XCDs has a private L2, so a device-scope release fence writes dirty L2 lines
+// back to memory.  Blocks write partials; a later kernel (stream order makes them
+// visible) reduces them.
 
-// Host-side launch helpers (defined in md_api.cpp).
+// Host-side launch helpers (defined in md_api.hip).
 int md_hip_status(hipError_t e);
+
+// Kernel timer (md_timer_arm): true once for the armed kernel id, with its events.
+bool md_timer_take(int kernel, hipEvent_t* start, hipEvent_t* stop);
+
+// Launch a kernel, bracketed by the timer's events when that kernel id is armed.
+#define MD_LAUNCH_TIMED(KID, KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                     \
+  do {                                                                                  \
+    hipEvent_t _t0, _t1;                                                                \
+    if (md_timer_take((KID), &_t0, &_t1))                                               \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, _t0, _t1, 0, __VA_ARGS__); \
+    else                                                                                \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);              \
+  } while (0)
 #define MD_LAUNCH_CHECK() \
   do {                                                    \
     hipError_t _e = hipGetLastError();                    \

@@ -1,0 +1,77 @@
+"""Differentiable EAM force matching on the GPU.
+
+A batch of fixed snapshots is binned and listed once; the forces of a trainable
+EAM (three uniform cubic B-splines) come from md_eam_forces, and the gradient of
+any loss of those forces with respect to the spline coefficients comes from the
+hand-written adjoint kernel md_eam_backward, wrapped in a torch.autograd.Function.
+Torch only evaluates the loss and holds memory.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _native as N
+from . import md
+
+
+class SnapshotBatch:
+    """All snapshots as one md_batch (one box per snapshot), binned and listed once."""
+
+    def __init__(self, snapshots, r_ns, precision=N.MD_FP64, lanes=4, max_neigh=128,
+                 device="cuda"):
+        boxes = [s.box for s in snapshots]
+        counts = [s.pos.shape[0] for s in snapshots]
+        pos = np.concatenate([s.pos for s in snapshots], axis=0)
+        self.plan = md.Plan(boxes, counts, r_ns, device)
+        self.state = md.State(self.plan, pos, None, precision)
+        self.nl = md.NeighborList(self.plan.n_atoms, max_neigh, lanes, device)
+        md.md_bin_cells(self.state, N.MD_ALWAYS)
+        md.md_build_neighbors(self.state, self.nl, N.MD_ALWAYS)
+        self.n = self.plan.n_atoms
+        self.n_snap = len(snapshots)
+        self.precision = precision
+        self.saved = torch.zeros((3, self.n), dtype=torch.float64, device=device)
+        self.bws = None
+        ids = self.state.id.long()
+        # current (cell) order -> original order permutation, for the caller's references
+        self.order_ids = ids
+
+    def to_current_order(self, a):
+        """[n, 3] array in the original atom order -> [3, n] tensor in the current order."""
+        t = torch.as_tensor(np.asarray(a, np.float64), device=self.state.pos.device)
+        return t[self.order_ids].t().contiguous()
+
+    def forces(self, pot: md.EAMPotential, saved=True):
+        md.md_eam_forces(self.state, pot, self.nl, saved=self.saved if saved else None)
+        return self.state.force.double()
+
+    def backward(self, pot: md.EAMPotential, grad_force):
+        g = grad_force.to(torch.float64).contiguous()
+        return md.md_eam_backward(self.state, pot, self.nl, self.saved, g)
+
+
+class EAMForces(torch.autograd.Function):
+    """forces = EAMForces.apply(coef, batch, potential): coef is the concatenated
+    (phi | rho | F) coefficient vector; the result is [3, n] in the batch's current order."""
+
+    @staticmethod
+    def forward(ctx, coef, batch: SnapshotBatch, pot: md.EAMPotential):
+        n0, n1 = pot.coef[0].shape[0], pot.coef[1].shape[0]
+        c = coef.detach().to(torch.float64)
+        pot.set_coefficients(c[:n0], c[n0:n0 + n1], c[n0 + n1:])
+        f = batch.forces(pot, saved=True).clone()
+        ctx.batch, ctx.pot = batch, pot
+        ctx.coef_dtype = coef.dtype
+        return f
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        g = ctx.batch.backward(ctx.pot, grad_f)
+        return g.to(ctx.coef_dtype), None, None
+
+
+def force_matching_loss(coef, batch, pot, f_ref):
+    """L = 1/(S N) sum |F - F_ref|^2 over all atoms of all snapshots."""
+    f = EAMForces.apply(coef, batch, pot)
+    return ((f - f_ref) ** 2).sum() / batch.n

@@ -1,0 +1,179 @@
+"""GPU parity of the batched path (many uneven boxes in one launch) and of the EAM
+adjoint (md_eam_backward) with the oracle.
+
+Tolerances: per-box FP64 energies 1e-12 relative to the oracle and 1e-9 eV/atom to the
+closed-form lattice sum (spline interpolation error); FP32 energies 1e-6 eV/atom;
+perfect-lattice forces |F| < 1e-10 eV/A (FP64); adjoint vs the oracle's chain-rule
+gradient 1e-10 relative (FP64 throughout).
+"""
+import numpy as np
+import pytest
+import torch
+
+import mdinputs as mi
+from oracle import adjoint as oadj
+from oracle import core
+from oracle import spline as osp
+from tests import lattice_sums as ls
+from tests.gpu_util import assert_same_sets, neighbor_sets_by_id
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def md():
+    from paper_2511_22951_amd import md as m
+    m.N.lib()
+    return m
+
+
+def _batch(md, reps, prec=0, lanes=4):
+    boxes = [r.box for r in reps]
+    counts = [len(r.pos) for r in reps]
+    plan = md.Plan(boxes, counts, 5.8)
+    st = md.State(plan, np.concatenate([r.pos for r in reps]), None, prec)
+    nl = md.NeighborList(plan.n_atoms, 128, lanes)
+    md.md_bin_cells(st)
+    md.md_build_neighbors(st, nl)
+    return plan, st, nl
+
+
+def test_batched_replicas_match_closed_form_and_single_calls(md):
+    reps = mi.cold_curve_replicas(n_rep=8, seed=31, n_min=4, n_max=7)
+    tab = mi.tabulate_eam(mi.EAM_CU)
+    pot = md.EAMPotential.from_table(tab)
+    plan, st, nl = _batch(md, reps)
+    ev = torch.zeros((1, len(reps), 8), dtype=torch.float64, device="cuda")
+    md.md_eam_forces(st, pot, nl, ev=ev)
+    st.check_flags()
+    e = ev.cpu().numpy()[0]
+    assert np.max(np.abs(st.forces())) < 1e-10
+    opot = core.EAMPotential.from_table(tab)
+    sets = neighbor_sets_by_id(st, nl)
+    off = 0
+    for r, rep in enumerate(reps):
+        n = len(rep.pos)
+        e_cf, _ = ls.eam_per_atom(rep.a, mi.EAM_CU)
+        assert abs(e[r, 0] / n - e_cf) < 1e-9, (r, rep.a)
+        ro = core.eam(rep.pos, rep.box, opot)
+        assert abs(e[r, 0] - ro.energy) < 1e-12 * abs(ro.energy)
+        assert np.max(np.abs(e[r, 1:7] - ro.virial)) < 1e-11 * np.max(np.abs(ro.virial))
+        cnt, want = core.neighbor_sets(rep.pos, rep.box, 5.8)
+        for i in range(n):
+            assert np.array_equal(sets[off + i] - off, want[i])
+        # the same box alone
+        p1, s1, n1 = _batch(md, [rep])
+        ev1 = torch.zeros((1, 1, 8), dtype=torch.float64, device="cuda")
+        md.md_eam_forces(s1, pot, n1, ev=ev1)
+        assert abs(ev1.cpu().numpy()[0, 0, 0] - e[r, 0]) < 1e-12 * abs(e[r, 0])
+        off += n
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cold_curve_64_replicas(md, prec):
+    reps = mi.cold_curve_replicas()
+    pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
+    plan, st, nl = _batch(md, reps, prec=prec)
+    ev = torch.zeros((1, len(reps), 8), dtype=torch.float64, device="cuda")
+    md.md_eam_forces(st, pot, nl, ev=ev)
+    st.check_flags()
+    e = ev.cpu().numpy()[0]
+    tol = 1e-9 if prec == 0 else 1e-6
+    for r, rep in enumerate(reps):
+        e_cf, _ = ls.eam_per_atom(rep.a, mi.EAM_CU)
+        assert abs(e[r, 0] / len(rep.pos) - e_cf) < tol, (r, rep.a, e[r, 0] / len(rep.pos), e_cf)
+        # pressure from the virial equals -dE/dV of the closed form (T = 0); the splines'
+        # first derivatives carry the O(h^3) interpolation error (~2e-8 relative to the
+        # individual pair and embedding terms, which are ~0.1 eV/A^3 per unit volume even
+        # where they cancel near equilibrium)
+        V = len(rep.pos) * rep.a ** 3 / 4
+        p_cf = -len(rep.pos) * ls.eam_dE_da(rep.a, mi.EAM_CU) / (3 * len(rep.pos) * rep.a ** 2 / 4)
+        ptol = (1e-7 if prec == 0 else 1e-5) * (abs(p_cf) + 0.1)
+        assert abs(e[r, 1:4].sum() / (3 * V) - p_cf) < ptol
+
+
+def test_batched_graph_replay_equals_eager(md):
+    reps = mi.cold_curve_replicas(n_rep=16, seed=33, n_min=4, n_max=6)
+    pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
+    plan, st, nl = _batch(md, reps)
+    ev = torch.zeros((1, len(reps), 8), dtype=torch.float64, device="cuda")
+    table = pot.table(0)
+    md.md_eam_forces(st, pot, nl, table=table, ev=ev)
+    torch.cuda.synchronize()
+    eager = ev.clone()
+    f_eager = st.force.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=s):
+        md.md_eam_forces(st, pot, nl, table=table, ev=ev)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(3):
+        ev.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ev, eager) and torch.equal(st.force, f_eager)
+
+
+# ----------------------------------------------------------------------------
+# adjoint
+# ----------------------------------------------------------------------------
+def _fm_problem(md, n_snap=3, cells=5, prec=0):
+    from paper_2511_22951_amd import fm
+    tab = mi.force_matching_tables()
+    noise = mi.coefficient_noise()
+    snaps = mi.force_matching_snapshots(n_snap=n_snap, cells=cells)
+    # oracle side
+    grids = tuple(oadj.Grid(tf.x_lo, tf.h, tf.K + 2) for tf in (tab.phi, tab.rho, tab.emb))
+    c_or = [osp.fit_table(tf) * noise[64 * b:64 * (b + 1)]
+            for b, tf in enumerate((tab.phi, tab.rho, tab.emb))]
+    osnaps = [oadj.Snapshot(s.pos, s.box, mi.EAM_CU.r_cut) for s in snaps]
+    # GPU side: its own fit of the same samples, times the same noise
+    fits = [md.md_spline_fit(tf.y, tf.h, tf.dy_lo, tf.dy_hi) for tf in (tab.phi, tab.rho, tab.emb)]
+    nz = torch.as_tensor(noise, device="cuda")
+    pot = md.EAMPotential(fits[0] * nz[:64], fits[1] * nz[64:128], fits[2] * nz[128:],
+                          tab.rho.x_lo, tab.rho.h, tab.emb.x_lo, tab.emb.h, mi.EAM_CU.r_cut)
+    batch = fm.SnapshotBatch(snaps, mi.EAM_CU.r_cut + 0.3, precision=prec)
+    return snaps, osnaps, grids, c_or, pot, batch
+
+
+def test_adjoint_vjp_matches_oracle(md):
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md)
+    G = [mi.random_cotangent(len(s.pos), seed=40 + k) for k, s in enumerate(snaps)]
+    want = np.concatenate(oadj.vjp(osnaps, c_or, grids, G))
+    batch.forces(pot, saved=True)
+    got = batch.backward(pot, batch.to_current_order(np.concatenate(G))).cpu().numpy()
+    batch.state.check_flags()
+    assert np.max(np.abs(got - want)) < 1e-10 * np.max(np.abs(want))
+    got2 = batch.backward(pot, batch.to_current_order(np.concatenate(G))).cpu().numpy()
+    assert np.array_equal(got, got2)  # run-to-run bitwise reproducible
+
+
+def test_force_matching_gradient_matches_oracle_and_fd(md):
+    from paper_2511_22951_amd import fm
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md)
+    # reference forces: oracle from the analytic EAM; GPU from the 2000-point table
+    apot = core.EAMPotential.analytic(mi.EAM_CU)
+    f_ref_or = [core.eam(s.pos, s.box, apot).force for s in snaps]
+    want = np.concatenate(oadj.gradient(osnaps, c_or, grids, f_ref_or))
+    ref_pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
+    f_ref = batch.forces(ref_pot, saved=False).clone()
+    coef = torch.cat([c.clone() for c in pot.coef]).requires_grad_(True)
+    loss = fm.force_matching_loss(coef, batch, pot, f_ref)
+    loss.backward()
+    got = coef.grad.cpu().numpy()
+    l_or = oadj.loss(osnaps, c_or, grids, f_ref_or)
+    assert abs(loss.item() - l_or) < 1e-6 * l_or
+    assert np.max(np.abs(got - want)) < 1e-6 * np.max(np.abs(want))
+    # FP64 central differences of the GPU loss, h = 1e-6
+    h = 1e-6
+    for k in (5, 20, 64 + 10, 64 + 40, 128 + 20, 128 + 33):
+        cp = coef.detach().clone()
+        cm = coef.detach().clone()
+        cp[k] += h
+        cm[k] -= h
+        lp = fm.force_matching_loss(cp, batch, pot, f_ref).item()
+        lm = fm.force_matching_loss(cm, batch, pot, f_ref).item()
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - got[k]) < 1e-5 * np.max(np.abs(got)), (k, fd, got[k])

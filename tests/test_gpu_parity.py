@@ -211,17 +211,19 @@ def test_eam_cu_trajectory_20_steps_and_graph_replay(mdmod):
 
 
 def test_piston_walls_match_oracle(mdmod):
-    """Walled box (periodic x, y; piston and top wall on z), 30 steps; a 10 km/s piston so
-    that atoms are reflected within the run."""
+    """Walled box (periodic x, y; piston and top wall on z), 40 steps; the piston starts at
+    z = 0.6 and moves at 2 km/s so that the bottom layer is reflected within the run."""
     from paper_2511_22951_amd.sim import Simulation
     s = mi.eam_aluminum_shock(nx=4, ny=4, nz=8)
-    s.walls = dict(s.walls, piston_v=100.0)
+    s.walls = dict(s.walls, piston_z0=0.6, piston_v=20.0)
     sim = Simulation(s, precision=0, lanes=4).setup()
-    sim.run(30)
+    sim.run(40)
     sim.state.check_flags()
     pot = core.EAMPotential.from_table(s.table)
-    x, v, f, hist = integrate.run_nve(s.pos, s.vel, s.box, s.mass, s.dt_ps, 30,
+    x, v, f, hist = integrate.run_nve(s.pos, s.vel, s.box, s.mass, s.dt_ps, 40,
                                       integrate.eam_force_fn(s.box, pot), walls=s.walls)
+    # the piston reached the bottom layer: some velocities were reflected
+    assert np.max(sim.state.velocities()[:, 2]) > 30.0
     d = sim.state.positions() - x
     L = np.array(s.box.len)
     per = np.array(s.box.periodic, bool)
