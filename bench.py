@@ -43,6 +43,12 @@ def parse():
     ap.add_argument("--kernel-samples", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device a few times (the known-size "
+                         "transfer that scales the FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--rebuild-every", type=int, default=-1,
+                    help="rebuild period k (0: on the half-skin threshold every step; "
+                         "-1: k chosen from the warm-up's rebuild intervals)")
     return ap.parse_args()
 
 
@@ -75,7 +81,22 @@ def run_path(system, prec, lanes, args):
     sim = Simulation(system, precision=prec, lanes=lanes, ev_cap=cap).setup()
     torch.cuda.synchronize()
     f0 = sim.state.forces()
-    sim.run(args.warmup, graph_steps=args.graph_steps)
+    # Warm-up on the threshold policy, recording when rebuilds happen; then rebuild every
+    # k steps with k = 3/5 of the shortest interval seen (the criterion stays verified).
+    k = args.rebuild_every
+    if k < 0:
+        marks = []
+        for _ in range(args.warmup):
+            sim.step()
+            marks.append(sim.state.read_flags()[1]["n_rebuilds"])
+        at = [s for s in range(1, len(marks)) if marks[s] > marks[s - 1]]
+        gaps = np.diff(at) if len(at) > 1 else np.array([10])
+        k = int(max(1, min(20, np.floor(0.6 * gaps.min()))))
+        print("[bench] warm-up rebuilds at steps %s -> rebuild every %d steps" % (at, k),
+              file=sys.stderr, flush=True)
+    else:
+        sim.run(args.warmup, graph_steps=args.graph_steps)
+    sim.set_rebuild_every(k)
     torch.cuda.synchronize()
     st0 = sim.state.read_flags()[1]
     e0 = torch.cuda.Event(enable_timing=True)
@@ -96,16 +117,19 @@ def run_path(system, prec, lanes, args):
     slope = float(np.polyfit(tps - tps[0], etot, 1)[0])
     # live kernel timing of the EAM passes and the kick-drift kernel
     kt = {}
-    for k in ("eam_force", "eam_density", "kick_drift"):
-        kt[k] = time_kernel(N, k, lambda: sim.step(), args.kernel_samples)
-    nneigh = sim.nl.nneigh[:n].double().mean().item()
+    for kname in ("eam_force", "eam_density", "kick_drift", "build"):
+        if kname == "build":  # one rebuild per sample
+            kt[kname] = time_kernel(N, kname, lambda: sim.rebuild(), max(3, args.kernel_samples // 10))
+        else:
+            kt[kname] = time_kernel(N, kname, lambda: sim.step(), args.kernel_samples)
+    nneigh = sim.nl.lengths().double().mean().item()
     torch.cuda.synchronize()
     return {
         "ms": ms, "steps": args.steps, "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"],
         "drift_ev_per_atom_ps": slope, "e0_per_atom": float(etot[0]),
         "energy_span_per_atom": float(np.max(etot) - np.min(etot)),
         "kernels_ms": kt, "mean_neigh": nneigh, "max_nneigh": info["max_nneigh"], "f0": f0,
-        "lanes": lanes,
+        "lanes": lanes, "rebuild_every": k,
     }
 
 
@@ -136,8 +160,22 @@ def cpu_baseline(system, f_gpu):
                       "%.1f s" % (n, dt)}, errs, float(r.energy / n)
 
 
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print("bench.py: this build targets one GPU; --gpus %d is not supported (run with "
               "--gpus 1)" % args.gpus, file=sys.stderr)
@@ -205,6 +243,9 @@ def main():
         paths[k] = {"atom_steps_per_s": n * args.steps / (r["ms"] * 1e-3),
                     "ms_per_step": r["ms"] / args.steps, "lanes": r["lanes"],
                     "rebuilds": r["rebuilds"], "mean_neigh": r["mean_neigh"],
+                    "rebuild_policy": ("every %d steps, half-skin criterion verified every step "
+                                       "(no violation)" % r["rebuild_every"]
+                                       if r["rebuild_every"] > 0 else "on the half-skin threshold"),
                     "nve_drift_eV_per_atom_ps": r["drift_ev_per_atom_ps"],
                     "energy_span_eV_per_atom": r["energy_span_per_atom"],
                     "kernel_us": {kk: 1e3 * v[0] for kk, v in r["kernels_ms"].items()},

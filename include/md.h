@@ -49,7 +49,9 @@ typedef enum {
   MD_ERR_WALL = -5,           /* an atom left a non-periodic extent */
   MD_ERR_NONFINITE = -6,      /* a position became NaN or infinite */
   MD_ERR_HIP = -7,            /* a HIP runtime call failed */
-  MD_ERR_WORKSPACE = -8       /* workspace or capacity too small */
+  MD_ERR_WORKSPACE = -8,      /* workspace or capacity too small */
+  MD_ERR_STALE_LIST = -9      /* an atom moved more than half the skin since the last list
+                                 build and no rebuild followed (forces may miss pairs) */
 } md_status;
 
 /* Device flag bits (md_read_flags output). */
@@ -57,6 +59,7 @@ typedef enum {
 #define MD_FLAG_TABLE_RANGE 2
 #define MD_FLAG_WALL 4
 #define MD_FLAG_NONFINITE 8
+#define MD_FLAG_STALE_LIST 16
 
 typedef enum { MD_FP64 = 0, MD_FP32 = 1 } md_precision; /* MD_FP32: FP32 pair math and
                                                           force accumulation, FP64
@@ -116,10 +119,13 @@ typedef struct md_batch {
  * rounded up to 64.  Entries are atom indices in the current (cell) order. */
 typedef struct md_nlist {
   int* neigh;   /* device [max_neigh * n_atoms_pad] */
-  int* nneigh;  /* device [n_atoms] */
+  int* nneigh;  /* device [n_atoms]: list length in bits 0..29; bit 30 (MD_NN_IMG) set when
+                   the atom's 3x3x3 cell block crosses a periodic boundary */
   int max_neigh;/* multiple of lanes */
   int lanes;    /* 1, 2, 4, 8 or 16 */
 } md_nlist;
+
+#define MD_NN_IMG (1 << 30)
 
 /* Uniform cubic B-spline on breakpoints x_lo + k h (k = 0..ncoef-3): ncoef
  * coefficients (FP64, device). */
@@ -155,9 +161,12 @@ typedef struct md_walls {
 } md_walls;
 
 /* Per-step thermodynamic record per box: {E_pot, W_xx, W_yy, W_zz, W_xy, W_xz,
- * W_yz, K} in eV, W the pair virial 1/2 sum_ij r_ij f_ij (Appendix), K the kinetic
- * energy (eq. 1.3). */
+ * W_yz, K}, W the pair virial 1/2 sum_ij r_ij f_ij (Appendix), K the kinetic
+ * energy (eq. 1.3).  Stored as signed 64-bit fixed point, MD_EV_SCALE units per
+ * eV (resolution 1.5e-11 eV, range +-1.3e8 eV): blocks add their sums with
+ * integer atomics, so the records are reproducible bit for bit. */
 #define MD_EV_LEN 8
+#define MD_EV_SCALE 68719476736.0 /* 2^36 */
 
 /* ---------------------------------------------------------------------------
  * Set-up (host)
@@ -209,7 +218,11 @@ int md_eam_prepare(const md_eam* p, md_precision prec, void* table, void* stream
  * (order inside a cell: ascending id).  Sets pos_ref = pos (the reference of
  * the displacement check).  cell_start[n_cells + 1] receives the first atom of
  * each cell.  With MD_IF_FLAGGED the kernels do nothing unless the last
- * md_verlet_step found a displacement above half the skin. */
+ * md_verlet_step found a displacement above half the skin (rebuild on the
+ * threshold, Sec. 1.4); MD_ALWAYS rebuilds unconditionally (e.g. every k steps,
+ * as in the benchmark of Sec. 1.7).  Either way the first force pass after a
+ * kick-drift verifies the criterion and sets MD_FLAG_STALE_LIST if an atom moved
+ * more than half the skin since the list was built. */
 int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos, double* vel, int* id,
                  double* pos_ref, int* cell_start, void* ws, void* ctl, void* stream);
 
@@ -229,7 +242,7 @@ int md_build_neighbors(const md_batch* b, md_rebuild_mode mode, const double* po
  * control block's step counter). */
 int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec, const double* pos,
                  const md_nlist* nl, void* force, double* vel, double inv_mass, double half_dt,
-                 double* ev, int ev_cap, void* ws, void* ctl, void* stream);
+                 long long* ev, int ev_cap, void* ws, void* ctl, void* stream);
 
 /* EAM forces: a density pass (rhobar_i = sum_j rho(r_ij), F(rhobar_i),
  * F'(rhobar_i), the energy) then a force pass
@@ -239,13 +252,13 @@ int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec, const dou
  * receives {rhobar, F', F''} as [3][n] FP64 for md_eam_backward. */
 int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec, const void* table,
                   const double* pos, const md_nlist* nl, void* force, double* saved,
-                  double* vel, double inv_mass, double half_dt, double* ev, int ev_cap, void* ws,
+                  double* vel, double inv_mass, double half_dt, long long* ev, int ev_cap, void* ws,
                   void* ctl, void* stream);
 
 /* Velocity Verlet (Sec. 1.5).  MD_KICK_DRIFT: v += half_dt f/m; x += dt v; walls
- * at t = (step + 1) dt; then the largest |x - pos_ref|^2 is compared with
- * (half_skin)^2 and the rebuild flag set for the next md_bin_cells; the step
- * counter advances.  MD_KICK: v += half_dt f/m only.  half_dt = dt / 2. */
+ * at t = (step + 1) dt; per-block maxima of |x - pos_ref|^2 are kept for the
+ * rebuild decision (compared with half_skin^2; half_skin < 0: no criterion).  The
+ * step counter advances in the next force pass.  MD_KICK: v += half_dt f/m only. */
 int md_verlet_step(const md_batch* b, md_verlet_phase phase, double dt, double* pos,
                    double* vel, const void* force, md_precision prec, double inv_mass,
                    const md_walls* walls, const double* pos_ref, double half_skin, void* ctl,

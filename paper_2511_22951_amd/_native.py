@@ -12,8 +12,11 @@ MD_FP64, MD_FP32 = 0, 1
 MD_ALWAYS, MD_IF_FLAGGED = 0, 1
 MD_KICK_DRIFT, MD_KICK = 0, 1
 MD_EV_LEN = 8
+MD_EV_SCALE = 2.0 ** 36  # fixed-point units per eV of the per-box records
 MD_TILE = 64
-FLAG_NEIGH_OVERFLOW, FLAG_TABLE_RANGE, FLAG_WALL, FLAG_NONFINITE = 1, 2, 4, 8
+MD_NN_IMG = 1 << 30
+FLAG_NEIGH_OVERFLOW, FLAG_TABLE_RANGE, FLAG_WALL, FLAG_NONFINITE, FLAG_STALE_LIST = 1, 2, 4, 8, 16
+MD_ERR_STALE_LIST = -9
 
 
 class MDError(RuntimeError):

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_adjoint(
     const double4 pi = pos[i];
     const double gix = G[i], giy = G[n + i], giz = G[2 * n + i];
     const double fp = saved[n + i], fpp = saved[2 * n + i];
-    const int nn = nneigh[i];
+    const int nn = nneigh[i] & MD_NN_MASK;
     const size_t stride = (size_t)npad * LANES;
     double tau = 0.0;
     const int* nb = neigh + (size_t)i * LANES + l;

@@ -128,7 +128,10 @@ __global__ void k_ctl_init(md_ctl_dev* ctl) {
     ctl->n_rebuilds = 0;
     ctl->max_nneigh = 0;
     ctl->n_dmax = 0;
-    ctl->pad[0] = ctl->pad[1] = 0;
+    ctl->step_next = 0;
+    ctl->pad = 0;
+    ctl->thr2 = -1.0;
+    ctl->pad2 = 0.0;
   }
   for (int k = threadIdx.x; k < MD_MAX_ATOM_BLOCKS; k += blockDim.x) ctl->dmax[k] = 0.0;
 }
@@ -169,6 +172,7 @@ extern "C" int md_read_flags(const void* ctl, int* host_out, void* stream) {
   host_out[2] = h.n_rebuilds;
   host_out[3] = h.max_nneigh;
   if (h.flags & MD_FLAG_NONFINITE) return MD_ERR_NONFINITE;
+  if (h.flags & MD_FLAG_STALE_LIST) return MD_ERR_STALE_LIST;
   if (h.flags & MD_FLAG_NEIGH_OVERFLOW) return MD_ERR_NEIGH_OVERFLOW;
   if (h.flags & MD_FLAG_WALL) return MD_ERR_WALL;
   if (h.flags & MD_FLAG_TABLE_RANGE) return MD_ERR_TABLE_RANGE;
@@ -186,6 +190,7 @@ extern "C" const char* md_status_string(int s) {
     case MD_ERR_NONFINITE: return "non-finite position";
     case MD_ERR_HIP: return "HIP runtime error";
     case MD_ERR_WORKSPACE: return "workspace or capacity too small";
+    case MD_ERR_STALE_LIST: return "an atom moved more than half the skin without a list rebuild";
     default: return "unknown status";
   }
 }

@@ -15,6 +15,8 @@
 // block / global reductions are FP64.
 #include <math.h>
 
+#include <type_traits>
+
 #include "md_internal.h"
 #include "md_tables.h"
 
@@ -22,7 +24,8 @@ namespace {
 
 template <typename R> __device__ __forceinline__ R rsqrt_r(R x);
 template <> __device__ __forceinline__ double rsqrt_r<double>(double x) { return rsqrt(x); }
-template <> __device__ __forceinline__ float rsqrt_r<float>(float x) { return rsqrtf(x); }
+// v_rsq_f32 (1 ulp); squared separations are never denormal here
+template <> __device__ __forceinline__ float rsqrt_r<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 
 struct TabGeom {
   double r_lo, r_inv_h, e_lo, e_inv_h;
@@ -43,76 +46,186 @@ __device__ __forceinline__ int tab_index(R x, R lo, R inv_h, int nint, R& t, boo
   return k;
 }
 
+// Same, for a pair that may lie beyond the cutoff (masked by the caller): the
+// index is clamped into the table and the range flag only counts pairs `in`.
+// u = x inv_h - lo inv_h is one multiply-add.
+template <typename R>
+__device__ __forceinline__ int tab_index_masked(R x, R inv_h, R lo_inv_h, int nint, bool in, R& t,
+                                                bool& oor) {
+  const R u = x * inv_h - lo_inv_h;
+  oor |= in && (u < (R)0);
+  const int k = min(max((int)u, 0), nint - 1);
+  t = u - (R)k;
+  return k;
+}
+
 struct Sep {
   double x, y, z;
 };
 
-// The tile's box, held in registers for the minimum image (block-uniform).
+// The tile's box for the minimum image, in scalar registers.  The inverse length
+// is 0 on non-periodic axes, where d - L rint(d * 0) = d: no selects needed.
 struct Img {
   double len[3], inv[3];
-  int per[3];
   __device__ __forceinline__ explicit Img(const md_domain* D) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       len[a] = D->len[a];
-      inv[a] = D->inv_len[a];
-      per[a] = D->periodic[a];
+      inv[a] = D->periodic[a] ? D->inv_len[a] : 0.0;
     }
   }
 };
 
-// r_j - r_i under the minimum image.
+// r_j - r_i, under the minimum image when IMG (atoms whose cell stencil crosses a
+// periodic boundary; for the others the plain difference is the minimum image,
+// since positions are wrapped at every rebuild and drift less than half a skin).
+template <bool IMG>
 __device__ __forceinline__ Sep separation(const Img& D, double4 pj, double4 pi) {
   Sep d{pj.x - pi.x, pj.y - pi.y, pj.z - pi.z};
-  if (D.per[0]) d.x -= D.len[0] * rint(d.x * D.inv[0]);
-  if (D.per[1]) d.y -= D.len[1] * rint(d.y * D.inv[1]);
-  if (D.per[2]) d.z -= D.len[2] * rint(d.z * D.inv[2]);
+  if (IMG) {
+    d.x -= D.len[0] * rint(d.x * D.inv[0]);
+    d.y -= D.len[1] * rint(d.y * D.inv[1]);
+    d.z -= D.len[2] * rint(d.z * D.inv[2]);
+  }
   return d;
 }
 
+// Blocks of the force passes: 1024 threads = TPB work tiles of 64 atoms x LANES lanes.
+constexpr int FBLOCK = 1024;
+template <int LANES> struct Shape {
+  static constexpr int TPB = FBLOCK / (64 * LANES);
+};
+
+// Where a thread sits: its tile (-1 if none), its atom slot and lane.
+struct Slot {
+  int t, a, l;
+};
+template <int LANES>
+__device__ __forceinline__ Slot force_slot(int n_tiles) {
+  constexpr int TPB = Shape<LANES>::TPB;
+  const int nlb = (n_tiles + TPB - 1) / TPB;
+  const int lb = md_remap_block(nlb);
+  Slot s;
+  const int within = threadIdx.x % (64 * LANES);
+  // a tile spans whole wavefronts, so the tile index is wave-uniform (scalar registers)
+  s.t = __builtin_amdgcn_readfirstlane(lb * TPB + (int)threadIdx.x / (64 * LANES));
+  if (lb >= nlb || s.t >= n_tiles) s.t = -1;
+  s.a = within / LANES;
+  s.l = within % LANES;
+  return s;
+}
+
+// Stage a table of nrows rows of W values of type R into LDS (16-byte moves).
+template <typename R, int W>
+__device__ __forceinline__ const R* stage_table(const R* g, int nrows, R* lds) {
+  const int n16 = nrows * W * (int)sizeof(R) / 16;
+  const float4* src = reinterpret_cast<const float4*>(g);
+  float4* dst = reinterpret_cast<float4*>(lds);
+  for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
+  __syncthreads();
+  return lds;
+}
+
+// Gathers address a uniform base plus a 32-bit byte offset (one VALU op per
+// address; arrays are below 4 GiB).
 __device__ __forceinline__ double4 load_xyz(const double4* pos, int j) {
   // Only x, y, z: the w slot may be written concurrently by the density pass.
-  const double2 a = *reinterpret_cast<const double2*>(pos + j);
-  const double c = reinterpret_cast<const double*>(pos + j)[2];
+  const char* p = reinterpret_cast<const char*>(pos) + (uint32_t)((uint32_t)j << 5);
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double c = *reinterpret_cast<const double*>(p + 16);
   return make_double4(a.x, a.y, c, 0.0);
 }
 
-// One block: per-box sums of the tile partials in fixed order, written to
-// ev[(step % ev_cap) * n_rep + rep].
-__global__ __launch_bounds__(1024) void k_ev_reduce(md_batch b, const double* partial, double* ev,
-                                                    int ev_cap, const md_ctl_dev* ctl) {
-  __shared__ double sh[MD_EV_LEN * 16];
-  const int step = ctl->step;
-  double* out = ev + (size_t)(step % ev_cap) * b.n_rep * MD_EV_LEN;
-  if (b.n_rep == 1) {
-    double v[MD_EV_LEN];
+__device__ __forceinline__ double4 load_rec(const double4* pos, int j) {
+  return *reinterpret_cast<const double4*>(reinterpret_cast<const char*>(pos) +
+                                           (uint32_t)((uint32_t)j << 5));
+}
+
+__device__ __forceinline__ int load_idx(const int* neigh, uint32_t e) {
+  return *reinterpret_cast<const int*>(reinterpret_cast<const char*>(neigh) + (e << 2));
+}
+
+// Visit the nn list entries of one atom handled by lane l of LANES: entry m sits
+// at element ((m / LANES) * npad + i) * LANES + l, i.e. e0 + (m / LANES) * stride.
+// U entries are in flight per lane: indices first, then records, then the math.
+template <int LANES, int U, typename Load, typename Pair>
+__device__ __forceinline__ void visit_list(const int* neigh, uint32_t e0, uint32_t stride, int l,
+                                           int nn, Load load, Pair pair) {
+  int m = l;
+  uint32_t e = e0;
+  for (; m + (U - 1) * LANES < nn; m += U * LANES) {
+    int j[U];
 #pragma unroll
-    for (int k = 0; k < MD_EV_LEN; ++k) v[k] = 0.0;
-    for (int t = threadIdx.x; t < b.n_tiles; t += blockDim.x)
+    for (int u = 0; u < U; ++u) j[u] = load_idx(neigh, e + u * stride);
+    e += U * stride;
+    decltype(load(0)) q[U];
 #pragma unroll
-      for (int k = 0; k < MD_EV_LEN; ++k) v[k] += partial[(size_t)t * MD_EV_LEN + k];
-    md_block_sum<MD_EV_LEN>(v, sh);
-    if (threadIdx.x == 0)
+    for (int u = 0; u < U; ++u) q[u] = load(j[u]);
 #pragma unroll
-      for (int k = 0; k < MD_EV_LEN; ++k) out[k] = v[k];
-  } else {
-    const int lane = threadIdx.x & (MD_WAVE - 1), wid = threadIdx.x / MD_WAVE;
-    const int nw = blockDim.x / MD_WAVE;
-    for (int r = wid; r < b.n_rep; r += nw) {
-      const int t0 = b.domains[r].tile_off, t1 = t0 + b.domains[r].n_tiles;
-      double v[MD_EV_LEN];
-#pragma unroll
-      for (int k = 0; k < MD_EV_LEN; ++k) v[k] = 0.0;
-      for (int t = t0 + lane; t < t1; t += MD_WAVE)
-#pragma unroll
-        for (int k = 0; k < MD_EV_LEN; ++k) v[k] += partial[(size_t)t * MD_EV_LEN + k];
-#pragma unroll
-      for (int k = 0; k < MD_EV_LEN; ++k) v[k] = md_wave_sum(v[k]);
-      if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < MD_EV_LEN; ++k) out[(size_t)r * MD_EV_LEN + k] = v[k];
-    }
+    for (int u = 0; u < U; ++u) pair(q[u]);
   }
+  for (; m < nn; m += LANES, e += stride) pair(load(load_idx(neigh, e)));
+}
+
+// F'(rhobar) travels to the force pass in the w slot of the position record: as a
+// double in FP64, as the float in its low word in FP32 (no conversion per pair).
+template <typename R> __device__ __forceinline__ void store_fp(double4* pos, int i, R v);
+template <> __device__ __forceinline__ void store_fp<double>(double4* pos, int i, double v) {
+  reinterpret_cast<double*>(pos + i)[3] = v;
+}
+template <> __device__ __forceinline__ void store_fp<float>(double4* pos, int i, float v) {
+  reinterpret_cast<double*>(pos + i)[3] = __hiloint2double(0, __float_as_int(v));
+}
+template <typename R> __device__ __forceinline__ R load_fp(double w);
+template <> __device__ __forceinline__ double load_fp<double>(double w) { return w; }
+template <> __device__ __forceinline__ float load_fp<float>(double w) {
+  return __int_as_float(__double2loint(w));
+}
+
+template <typename R> __device__ __forceinline__ R sqrt_r(R x);
+template <> __device__ __forceinline__ double sqrt_r<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float sqrt_r<float>(float x) {
+  return x * __builtin_amdgcn_rsqf(x);
+}
+
+// Per-box records are 64-bit fixed point (MD_EV_SCALE units per eV): integer
+// additions are associative, so atomically accumulated records are bit-for-bit
+// reproducible whatever order the blocks finish in.
+__device__ __forceinline__ long long to_fixed(double v) {
+  return (long long)rint(v * MD_EV_SCALE);
+}
+
+// Add a block's per-tile sums (tsum[g][k], g < TPB) into the record slot: tiles
+// of one box are combined first, then one atomic per (box, component).
+template <int TPB>
+__device__ __forceinline__ void accumulate_record(const md_batch& b, int lb, int nlb,
+                                                  const double* tsum, long long* slot) {
+  const int k = threadIdx.x;
+  if (k >= MD_EV_LEN || lb >= nlb) return;
+  int rep = -1;
+  double acc = 0.0;
+  for (int g = 0; g < TPB; ++g) {
+    const int t = lb * TPB + g;
+    if (t >= b.n_tiles) break;
+    const int r = b.tiles[t].rep;
+    if (r != rep) {
+      if (rep >= 0) atomicAdd((unsigned long long*)&slot[(size_t)rep * MD_EV_LEN + k],
+                              (unsigned long long)to_fixed(acc));
+      rep = r;
+      acc = 0.0;
+    }
+    acc += tsum[g * MD_EV_LEN + k];
+  }
+  if (rep >= 0)
+    atomicAdd((unsigned long long*)&slot[(size_t)rep * MD_EV_LEN + k],
+              (unsigned long long)to_fixed(acc));
+}
+
+// Zero the record slot of the current step (one block, before any accumulation).
+__device__ __forceinline__ void zero_record(const md_batch& b, long long* ev, int ev_cap,
+                                            int step) {
+  long long* slot = ev + (size_t)(step % ev_cap) * b.n_rep * MD_EV_LEN;
+  for (int q = threadIdx.x; q < b.n_rep * MD_EV_LEN; q += blockDim.x) slot[q] = 0;
 }
 
 // Epilogue shared by the LJ and EAM force kernels: write the force, apply the
@@ -137,60 +250,81 @@ __device__ __forceinline__ double write_force_kick(int i, int n, R fx, R fy, R f
   return 0.5 / (inv_mass * MD_ACCEL) * (vx * vx + vy * vy + vz * vz);
 }
 
+// Block 0 of the first force kernel of a step: advance the step counter to the
+// value the kick-drift published, and verify the neighbour list: if an atom has
+// moved more than half the skin since the list was built and no rebuild followed,
+// the list may miss pairs (MD_FLAG_STALE_LIST).
+__device__ __forceinline__ void step_bookkeeping(md_ctl_dev* ctl) {
+  if (blockIdx.x != 0) return;
+  const bool stale = md_displacement_exceeded(ctl);
+  if (threadIdx.x == 0) {
+    if (stale) md_flag(ctl, MD_FLAG_STALE_LIST);
+    ctl->step = ctl->step_next;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // EAM pass 1: rhobar_i = sum_j rho(r_ij), F'(rhobar_i) into pos[i].w, energy.
 // ---------------------------------------------------------------------------
-template <typename R, int LANES, bool EV>
-__global__ __launch_bounds__(64 * LANES) void k_eam_density(
+template <typename R, int LANES, bool EV, bool TLDS>
+__global__ __launch_bounds__(FBLOCK) void k_eam_density(
     md_batch b, double4* pos, const int* __restrict__ neigh, const int* __restrict__ nneigh,
-    int npad, const R* __restrict__ rtab, const R* __restrict__ etab, TabGeom g, R rc2,
-    double* saved, double* partial, md_ctl_dev* ctl) {
+    int npad, const R* __restrict__ rtab_g, const R* __restrict__ etab, TabGeom g, R rc2,
+    double* saved, double* partial, long long* ev, int ev_cap, md_ctl_dev* ctl) {
   constexpr int U = 4;  // neighbours in flight per lane
+  extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
-  const int t = md_remap_block(b.n_tiles);
-  if (t >= b.n_tiles) return;  // padding block: no block-wide work follows
-  const md_tile T = b.tiles[t];
-  const Img D(&b.domains[T.rep]);
-  const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
+  const R* rtab = TLDS ? stage_table<R, MD_RTAB_W>(rtab_g, g.nr, (R*)s_dyn) : rtab_g;
+  if (EV && blockIdx.x == 0) zero_record(b, ev, ev_cap, ctl->step_next);
+  step_bookkeeping(ctl);
+  const Slot S = force_slot<LANES>(b.n_tiles);
   double e_acc = 0.0;
   bool oor = false;
-  if (a < T.count) {
-    const int i = T.first + a;
-    const double4 pi = load_xyz(pos, i);
-    const int nn = nneigh[i];
-    const R rlo = (R)g.r_lo, rih = (R)g.r_inv_h;
-    R rho = 0, phi = 0;
-    const int* nb = neigh + (size_t)i * LANES + l;
-    const size_t stride = (size_t)npad * LANES;
-    auto pair = [&](double4 pj) {
-      const Sep d = separation(D, pj, pi);
-      const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
-      const R r2 = x * x + y * y + z * z;
-      if (r2 < rc2) {
-        const R r = sqrt(r2);
-        R tt;
-        const int k = tab_index<R>(r, rlo, rih, g.nr, tt, oor);
-        const R* row = rtab + (size_t)k * MD_RTAB_W;
-        rho += ((row[3] * tt + row[2]) * tt + row[1]) * tt + row[0];
-        if (EV) phi += ((row[7] * tt + row[6]) * tt + row[5]) * tt + row[4];
-      }
-    };
-    int m = l;
-    for (; m + (U - 1) * LANES < nn; m += U * LANES) {
-      int j[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) j[u] = nb[u * stride];
-      nb += U * stride;
-      double4 pj[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) pj[u] = load_xyz(pos, j[u]);
-#pragma unroll
-      for (int u = 0; u < U; ++u) pair(pj[u]);
+  int i = -1, nn = 0, raw = 0;
+  md_tile T{0, 0, 0, 0};
+  if (S.t >= 0) {
+    T = b.tiles[S.t];
+    if (S.a < T.count) {
+      i = T.first + S.a;
+      raw = nneigh[i];
+      nn = raw & MD_NN_MASK;
     }
-    for (; m < nn; m += LANES, nb += stride) pair(load_xyz(pos, *nb));
-    rho = md_group_sum<LANES>(rho);
+  }
+  const bool wimg = __any(raw & MD_NN_IMG);
+  R rho = 0, phi = 0;
+  if (i >= 0) {
+    const Img D(&b.domains[T.rep]);
+    const double4 pi = load_xyz(pos, i);
+    const R rih = (R)g.r_inv_h, rloh = (R)(g.r_lo * g.r_inv_h);
+    const uint32_t e0 = (uint32_t)i * LANES + S.l, stride = (uint32_t)npad * LANES;
+    auto run = [&](auto img_tag) {
+      constexpr bool IMG = decltype(img_tag)::value;
+      auto pair = [&](double4 pj) {
+        const Sep d = separation<IMG>(D, pj, pi);
+        const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
+        const R r2 = x * x + y * y + z * z;
+        const bool in = r2 < rc2;  // branch-free: pairs beyond r_c are masked
+        const R r = sqrt_r<R>(r2);
+        R tt;
+        const int k = tab_index_masked<R>(r, rih, rloh, g.nr, in, tt, oor);
+        const R* row = rtab + k * MD_RTAB_W;
+        const R vr = ((row[3] * tt + row[2]) * tt + row[1]) * tt + row[0];
+        rho += in ? vr : (R)0;
+        if (EV) {
+          const R vp = ((row[7] * tt + row[6]) * tt + row[5]) * tt + row[4];
+          phi += in ? vp : (R)0;
+        }
+      };
+      visit_list<LANES, U>(neigh, e0, stride, S.l, nn,
+                           [&](int j) { return load_xyz(pos, j); }, pair);
+    };
+    if (wimg) run(std::true_type{});
+    else run(std::false_type{});
+  }
+  rho = md_group_sum<LANES>(rho);
+  if (i >= 0) {
     if (EV) e_acc += 0.5 * (double)phi;
-    if (l == 0) {
+    if (S.l == 0) {
       R tt;
       const R u = (rho - (R)g.e_lo) * (R)g.e_inv_h;
       if (u < (R)0 || u > (R)g.ne) oor = true;
@@ -198,7 +332,7 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_density(
       const R* row = etab + (size_t)k * MD_ETAB_W;
       const R F = ((row[3] * tt + row[2]) * tt + row[1]) * tt + row[0];
       const R F1 = (row[6] * tt + row[5]) * tt + row[4];
-      reinterpret_cast<double*>(pos + i)[3] = (double)F1;
+      store_fp<R>(pos, i, F1);
       if (saved) {
         const int n = b.n_atoms;
         saved[i] = (double)rho;
@@ -213,54 +347,72 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_density(
   }
   if (EV) {
     double v[1] = {e_acc};
-    md_block_sum<1>(v, sh);
-    if (threadIdx.x == 0) partial[(size_t)t * MD_EV_LEN] = v[0];
+    double res;
+    int gg, kk;
+    if (md_group_waves_sum<1>(v, LANES, sh, res, gg, kk)) {
+      constexpr int TPB = Shape<LANES>::TPB;
+      const int nlb = (b.n_tiles + TPB - 1) / TPB;
+      const int lb = md_remap_block(nlb);
+      const int t = lb * TPB + gg;
+      if (lb < nlb && t < b.n_tiles) partial[(size_t)t * MD_EV_LEN] = res;
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // EAM pass 2: f_i = sum_j [phi'(r) + (F'_i + F'_j) rho'(r)] (r_j - r_i) / r,
-// virial, trailing kick, kinetic energy, and the final per-box reduction.
+// virial, trailing kick and kinetic energy.
 // ---------------------------------------------------------------------------
-template <typename R, int LANES, bool EV>
-__global__ __launch_bounds__(64 * LANES) void k_eam_force(
+template <typename R, int LANES, bool EV, bool TLDS>
+__global__ __launch_bounds__(FBLOCK) void k_eam_force(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
-    const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab, TabGeom g, R rc2,
-    R* force, double* vel, double inv_mass, double half_dt, double* partial, md_ctl_dev* ctl) {
-  constexpr int U = 4;  // neighbours in flight per lane
+    const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, TabGeom g, R rc2,
+    R* force, double* vel, double inv_mass, double half_dt, const double* partial, long long* ev,
+    int ev_cap, md_ctl_dev* ctl) {
+  constexpr int U = 4;
+  extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
-  const int t = md_remap_block(b.n_tiles);
-  if (t >= b.n_tiles) return;
-  const md_tile T = b.tiles[t];
-  const Img D(&b.domains[T.rep]);
-  const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
+  __shared__ double tsum[MD_EV_LEN * 16];
+  const R* ftab = TLDS ? stage_table<R, MD_FTAB_W>(ftab_g, g.nr, (R*)s_dyn) : ftab_g;
+  const Slot S = force_slot<LANES>(b.n_tiles);
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // W xx yy zz xy xz yz, K
   bool oor = false;
   R fx = 0, fy = 0, fz = 0;
   R w[6] = {0, 0, 0, 0, 0, 0};
-  int i = -1;
-  if (a < T.count) {
-    i = T.first + a;
+  int i = -1, nn = 0, raw = 0;
+  md_tile T{0, 0, 0, 0};
+  if (S.t >= 0) {
+    T = b.tiles[S.t];
+    if (S.a < T.count) {
+      i = T.first + S.a;
+      raw = nneigh[i];
+      nn = raw & MD_NN_MASK;
+    }
+  }
+  const bool wimg = __any(raw & MD_NN_IMG);
+  if (i >= 0) {
+    const Img D(&b.domains[T.rep]);
     const double4 pi = pos[i];
-    const R fpi = (R)pi.w;
-    const int nn = nneigh[i];
-    const R rlo = (R)g.r_lo, rih = (R)g.r_inv_h;
-    const int* nb = neigh + (size_t)i * LANES + l;
-    const size_t stride = (size_t)npad * LANES;
-    auto pair = [&](double4 pj) {
-      const Sep d = separation(D, pj, pi);
-      const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
-      const R r2 = x * x + y * y + z * z;
-      if (r2 < rc2) {
+    const R fpi = load_fp<R>(pi.w);
+    const R rih = (R)g.r_inv_h, rloh = (R)(g.r_lo * g.r_inv_h);
+    const uint32_t e0 = (uint32_t)i * LANES + S.l, stride = (uint32_t)npad * LANES;
+    auto run = [&](auto img_tag) {
+      constexpr bool IMG = decltype(img_tag)::value;
+      auto pair = [&](double4 pj) {
+        const Sep d = separation<IMG>(D, pj, pi);
+        const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
+        const R r2 = x * x + y * y + z * z;
+        const bool in = r2 < rc2;  // branch-free: pairs beyond r_c are masked
         const R rinv = rsqrt_r<R>(r2);
         const R r = r2 * rinv;
         R tt;
-        const int k = tab_index<R>(r, rlo, rih, g.nr, tt, oor);
-        const R* row = ftab + (size_t)k * MD_FTAB_W;
+        const int k = tab_index_masked<R>(r, rih, rloh, g.nr, in, tt, oor);
+        const R* row = ftab + k * MD_FTAB_W;
         const R dphi = (row[2] * tt + row[1]) * tt + row[0];
         const R drho = (row[5] * tt + row[4]) * tt + row[3];
         // force on i from j: s (r_j - r_i), s = [phi' + (F'_i + F'_j) rho'] / r
-        const R s = (dphi + (fpi + (R)pj.w) * drho) * rinv;
+        const R s0 = (dphi + (fpi + load_fp<R>(pj.w)) * drho) * rinv;
+        const R s = in ? s0 : (R)0;
         fx += s * x;
         fy += s * y;
         fz += s * z;
@@ -272,26 +424,17 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_force(
           w[4] -= s * x * z;
           w[5] -= s * y * z;
         }
-      }
+      };
+      visit_list<LANES, U>(neigh, e0, stride, S.l, nn, [&](int j) { return load_rec(pos, j); },
+                           pair);
     };
-    int m = l;
-    for (; m + (U - 1) * LANES < nn; m += U * LANES) {
-      int j[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) j[u] = nb[u * stride];
-      nb += U * stride;
-      double4 pj[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) pj[u] = pos[j[u]];
-#pragma unroll
-      for (int u = 0; u < U; ++u) pair(pj[u]);
-    }
-    for (; m < nn; m += LANES, nb += stride) pair(pos[*nb]);
+    if (wimg) run(std::true_type{});
+    else run(std::false_type{});
   }
   fx = md_group_sum<LANES>(fx);
   fy = md_group_sum<LANES>(fy);
   fz = md_group_sum<LANES>(fz);
-  if (i >= 0 && l == 0)
+  if (i >= 0 && S.l == 0)
     acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
   if (EV)
 #pragma unroll
@@ -300,10 +443,45 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_force(
     if ((threadIdx.x & (MD_WAVE - 1)) == 0) md_flag(ctl, MD_FLAG_TABLE_RANGE);
   }
   if (EV) {
-    md_block_sum<7>(acc, sh);
-    if (threadIdx.x == 0)
+    double res;
+    int gg, kk;
+    constexpr int TPB = Shape<LANES>::TPB;
+    const int nlb = (b.n_tiles + TPB - 1) / TPB;
+    const int lb = md_remap_block(nlb);
+    if (md_group_waves_sum<7>(acc, LANES, sh, res, gg, kk)) {
+      tsum[gg * MD_EV_LEN + 1 + kk] = res;
+      const int t = lb * TPB + gg;
+      // the tile's energy from the density pass
+      if (kk == 0) tsum[gg * MD_EV_LEN] = (lb < nlb && t < b.n_tiles) ? partial[(size_t)t * MD_EV_LEN] : 0.0;
+    }
+    __syncthreads();
+    accumulate_record<TPB>(b, lb, nlb, tsum, ev + (size_t)(ctl->step % ev_cap) * b.n_rep * MD_EV_LEN);
+  }
+}
+
+// One block: per-box sums of the LJ tile partials in fixed order, written as a
+// fixed-point record to ev[(step % ev_cap) * n_rep + rep].
+__global__ __launch_bounds__(1024) void k_ev_reduce(md_batch b, const double* partial,
+                                                    long long* ev, int ev_cap,
+                                                    const md_ctl_dev* ctl) {
+  __shared__ double sh[MD_EV_LEN * 16];
+  const int step = ctl->step;
+  long long* out = ev + (size_t)(step % ev_cap) * b.n_rep * MD_EV_LEN;
+  const int lane = threadIdx.x & (MD_WAVE - 1), wid = threadIdx.x / MD_WAVE;
+  const int nw = blockDim.x / MD_WAVE;
+  for (int r = wid; r < b.n_rep; r += nw) {
+    const int t0 = b.domains[r].tile_off, t1 = t0 + b.domains[r].n_tiles;
+    double v[MD_EV_LEN];
 #pragma unroll
-      for (int k = 0; k < 7; ++k) partial[(size_t)t * MD_EV_LEN + 1 + k] = acc[k];
+    for (int k = 0; k < MD_EV_LEN; ++k) v[k] = 0.0;
+    for (int t = t0 + lane; t < t1; t += MD_WAVE)
+#pragma unroll
+      for (int k = 0; k < MD_EV_LEN; ++k) v[k] += partial[(size_t)t * MD_EV_LEN + k];
+#pragma unroll
+    for (int k = 0; k < MD_EV_LEN; ++k) v[k] = md_wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < MD_EV_LEN; ++k) out[(size_t)r * MD_EV_LEN + k] = to_fixed(v[k]);
   }
 }
 
@@ -315,80 +493,84 @@ struct LJc {
 };
 
 template <typename R, int LANES, bool EV>
-__global__ __launch_bounds__(64 * LANES) void k_lj(
+__global__ __launch_bounds__(FBLOCK) void k_lj(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, LJc c, R rc2, R* force, double* vel,
     double inv_mass, double half_dt, double* partial, md_ctl_dev* ctl) {
   constexpr int U = 4;
   __shared__ double sh[MD_EV_LEN * 16];
-  const int t = md_remap_block(b.n_tiles);
-  if (t >= b.n_tiles) return;
-  const md_tile T = b.tiles[t];
-  const Img D(&b.domains[T.rep]);
-  const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
+  step_bookkeeping(ctl);
+  const Slot S = force_slot<LANES>(b.n_tiles);
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // E, W xx yy zz xy xz yz, K
   const R sig2 = (R)c.sig2, eps4 = (R)c.eps4, eps24 = (R)c.eps24, ucut = (R)c.ucut;
   R fx = 0, fy = 0, fz = 0, e = 0;
   R w[6] = {0, 0, 0, 0, 0, 0};
-  int i = -1;
-  if (a < T.count) {
-    i = T.first + a;
-    const double4 pi = pos[i];
-    const int nn = nneigh[i];
-    const int* nb = neigh + (size_t)i * LANES + l;
-    const size_t stride = (size_t)npad * LANES;
-    auto pair = [&](double4 pj) {
-      const Sep d = separation(D, pj, pi);
-      const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
-      const R r2 = x * x + y * y + z * z;
-      if (r2 < rc2) {
-        const R ir2 = (R)1 / r2;
-        const R sr2 = sig2 * ir2;
-        const R sr6 = sr2 * sr2 * sr2;
-        const R sr12 = sr6 * sr6;
-        // f_i = -dU/dr r_ij / r = -24 eps (2 sr12 - sr6) / r^2 (r_j - r_i)
-        const R s = -eps24 * ((R)2 * sr12 - sr6) * ir2;
-        fx += s * x;
-        fy += s * y;
-        fz += s * z;
-        if (EV) {
-          e += eps4 * (sr12 - sr6) - ucut;
-          w[0] -= s * x * x;
-          w[1] -= s * y * y;
-          w[2] -= s * z * z;
-          w[3] -= s * x * y;
-          w[4] -= s * x * z;
-          w[5] -= s * y * z;
-        }
-      }
-    };
-    int m = l;
-    for (; m + (U - 1) * LANES < nn; m += U * LANES) {
-      int j[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) j[u] = nb[u * stride];
-      nb += U * stride;
-      double4 pj[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) pj[u] = pos[j[u]];
-#pragma unroll
-      for (int u = 0; u < U; ++u) pair(pj[u]);
+  int i = -1, nn = 0, raw = 0;
+  md_tile T{0, 0, 0, 0};
+  if (S.t >= 0) {
+    T = b.tiles[S.t];
+    if (S.a < T.count) {
+      i = T.first + S.a;
+      raw = nneigh[i];
+      nn = raw & MD_NN_MASK;
     }
-    for (; m < nn; m += LANES, nb += stride) pair(pos[*nb]);
+  }
+  const bool wimg = __any(raw & MD_NN_IMG);
+  if (i >= 0) {
+    const Img D(&b.domains[T.rep]);
+    const double4 pi = pos[i];
+    const uint32_t e0 = (uint32_t)i * LANES + S.l, stride = (uint32_t)npad * LANES;
+    auto run = [&](auto img_tag) {
+      constexpr bool IMG = decltype(img_tag)::value;
+      auto pair = [&](double4 pj) {
+        const Sep d = separation<IMG>(D, pj, pi);
+        const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
+        const R r2 = x * x + y * y + z * z;
+        if (r2 < rc2) {
+          const R ir2 = (R)1 / r2;
+          const R sr2 = sig2 * ir2;
+          const R sr6 = sr2 * sr2 * sr2;
+          const R sr12 = sr6 * sr6;
+          // f_i = -dU/dr r_ij / r = -24 eps (2 sr12 - sr6) / r^2 (r_j - r_i)
+          const R s = -eps24 * ((R)2 * sr12 - sr6) * ir2;
+          fx += s * x;
+          fy += s * y;
+          fz += s * z;
+          if (EV) {
+            e += eps4 * (sr12 - sr6) - ucut;
+            w[0] -= s * x * x;
+            w[1] -= s * y * y;
+            w[2] -= s * z * z;
+            w[3] -= s * x * y;
+            w[4] -= s * x * z;
+            w[5] -= s * y * z;
+          }
+        }
+      };
+      visit_list<LANES, U>(neigh, e0, stride, S.l, nn, [&](int j) { return load_rec(pos, j); },
+                           pair);
+    };
+    if (wimg) run(std::true_type{});
+    else run(std::false_type{});
   }
   fx = md_group_sum<LANES>(fx);
   fy = md_group_sum<LANES>(fy);
   fz = md_group_sum<LANES>(fz);
-  if (i >= 0 && l == 0)
+  if (i >= 0 && S.l == 0)
     acc[7] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
   if (EV) {
     acc[0] = 0.5 * (double)e;
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[1 + k] = 0.5 * (double)w[k];
-    md_block_sum<8>(acc, sh);
-    if (threadIdx.x == 0)
-#pragma unroll
-      for (int k = 0; k < 8; ++k) partial[(size_t)t * MD_EV_LEN + k] = acc[k];
+    double res;
+    int gg, kk;
+    if (md_group_waves_sum<8>(acc, LANES, sh, res, gg, kk)) {
+      constexpr int TPB = Shape<LANES>::TPB;
+      const int nlb = (b.n_tiles + TPB - 1) / TPB;
+      const int lb = md_remap_block(nlb);
+      const int t = lb * TPB + gg;
+      if (lb < nlb && t < b.n_tiles) partial[(size_t)t * MD_EV_LEN + kk] = res;
+    }
   }
 }
 
@@ -407,10 +589,17 @@ bool nlist_ok(const md_nlist* nl) {
   return nl->max_neigh >= L && nl->max_neigh % L == 0;
 }
 
+// FP32 tables are staged in LDS when they fit the default dynamic LDS limit
+// (2 blocks of 1024 threads per CU); FP64 tables are read through the caches.
+template <typename R>
+bool table_in_lds(int nrows, int width) {
+  return sizeof(R) == 4 && (size_t)nrows * width * sizeof(R) <= 65536;
+}
+
 template <typename R, int LANES>
 void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_table_layout& TL,
                 const double* pos, const md_nlist& nl, void* force, double* saved, double* vel,
-                double inv_mass, double half_dt, double* ev, int ev_cap, double* partial,
+                double inv_mass, double half_dt, long long* ev, int ev_cap, double* partial,
                 md_ctl_dev* ctl, hipStream_t st) {
   TabGeom g;
   g.r_lo = p.rho.x_lo;
@@ -420,32 +609,37 @@ void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_ta
   g.nr = p.rho.ncoef - 3;
   g.ne = p.emb.ncoef - 3;
   const R rc2 = (R)(p.r_cut * p.r_cut);
-  const dim3 grid(md_grid_blocks(b.n_tiles)), block(64 * LANES);
+  constexpr int TPB = Shape<LANES>::TPB;
+  const dim3 grid(md_grid_blocks((b.n_tiles + TPB - 1) / TPB)), block(FBLOCK);
   const int npad = md_npad(b.n_atoms);
   const R* rtab = (const R*)(tab + TL.rtab);
   const R* ftab = (const R*)(tab + TL.ftab);
   const R* etab = (const R*)(tab + TL.etab);
+  const bool ld = table_in_lds<R>(g.nr, MD_RTAB_W);
+  const size_t lds_d = ld ? (size_t)g.nr * MD_RTAB_W * sizeof(R) : 0;
+  const size_t lds_f = ld ? (size_t)g.nr * MD_FTAB_W * sizeof(R) : 0;
+#define MD_EAM_LAUNCH(EVB, TL_)                                                                 \
+  do {                                                                                         \
+    MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density<R, LANES, EVB, TL_>), grid, block,    \
+                    lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g, rc2, \
+                    saved, partial, ev, ev_cap, ctl);                                          \
+    MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force<R, LANES, EVB, TL_>), grid, block, lds_f, \
+                    st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g, rc2,        \
+                    (R*)force, vel, inv_mass, half_dt, partial, ev, ev_cap, ctl);              \
+  } while (0)
   if (ev) {
-    MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density<R, LANES, true>), grid, block, 0, st, b,
-                    (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g, rc2, saved, partial,
-                    ctl);
-    MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force<R, LANES, true>), grid, block, 0, st, b,
-                    (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g, rc2, (R*)force, vel,
-                    inv_mass, half_dt, partial, ctl);
-    hipLaunchKernelGGL(k_ev_reduce, dim3(1), dim3(1024), 0, st, b, partial, ev, ev_cap, ctl);
+    if (ld) MD_EAM_LAUNCH(true, true);
+    else MD_EAM_LAUNCH(true, false);
   } else {
-    MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density<R, LANES, false>), grid, block, 0, st,
-                    b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g, rc2, saved,
-                    partial, ctl);
-    MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force<R, LANES, false>), grid, block, 0, st, b,
-                    (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g, rc2, (R*)force, vel,
-                    inv_mass, half_dt, partial, ctl);
+    if (ld) MD_EAM_LAUNCH(false, true);
+    else MD_EAM_LAUNCH(false, false);
   }
+#undef MD_EAM_LAUNCH
 }
 
 template <typename R, int LANES>
 void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nlist& nl,
-               void* force, double* vel, double inv_mass, double half_dt, double* ev, int ev_cap,
+               void* force, double* vel, double inv_mass, double half_dt, long long* ev, int ev_cap,
                double* partial, md_ctl_dev* ctl, hipStream_t st) {
   LJc c;
   c.sig2 = p.sigma * p.sigma;
@@ -454,7 +648,8 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
   const double src6 = pow(p.sigma / p.r_cut, 6.0);
   c.ucut = 4.0 * p.eps * (src6 * src6 - src6);
   const R rc2 = (R)(p.r_cut * p.r_cut);
-  const dim3 grid(md_grid_blocks(b.n_tiles)), block(64 * LANES);
+  constexpr int TPB = Shape<LANES>::TPB;
+  const dim3 grid(md_grid_blocks((b.n_tiles + TPB - 1) / TPB)), block(FBLOCK);
   const int npad = md_npad(b.n_atoms);
   if (ev) {
     MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, true>), grid, block, 0, st, b,
@@ -482,7 +677,7 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
 extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec,
                              const void* table, const double* pos, const md_nlist* nl,
                              void* force, double* saved, double* vel, double inv_mass,
-                             double half_dt, double* ev, int ev_cap, void* ws, void* ctl,
+                             double half_dt, long long* ev, int ev_cap, void* ws, void* ctl,
                              void* stream) {
   if (!batch_ok(b) || !md_eam_ok(p) || !table || !pos || !nlist_ok(nl) || !force || !ws || !ctl)
     return MD_ERR_ARG;
@@ -497,11 +692,11 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   md_ctl_dev* c = (md_ctl_dev*)ctl;
   if (prec == MD_FP32) {
     MD_DISPATCH_LANES(nl->lanes, (launch_eam<float, L_>(*b, *p, (const char*)table, TL, pos, *nl,
-                                                        force, saved, vel, inv_mass, half_dt, ev,
+                                                        force, saved, vel, inv_mass, half_dt, (long long*)ev,
                                                         ev_cap, partial, c, st)));
   } else {
     MD_DISPATCH_LANES(nl->lanes, (launch_eam<double, L_>(*b, *p, (const char*)table, TL, pos, *nl,
-                                                         force, saved, vel, inv_mass, half_dt, ev,
+                                                         force, saved, vel, inv_mass, half_dt, (long long*)ev,
                                                          ev_cap, partial, c, st)));
   }
   MD_LAUNCH_CHECK();
@@ -510,7 +705,7 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
 
 extern "C" int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec,
                             const double* pos, const md_nlist* nl, void* force, double* vel,
-                            double inv_mass, double half_dt, double* ev, int ev_cap, void* ws,
+                            double inv_mass, double half_dt, long long* ev, int ev_cap, void* ws,
                             void* ctl, void* stream) {
   if (!batch_ok(b) || !p || !pos || !nlist_ok(nl) || !force || !ws || !ctl) return MD_ERR_ARG;
   if (!(p->sigma > 0.0) || !(p->r_cut > 0.0)) return MD_ERR_ARG;
@@ -524,10 +719,10 @@ extern "C" int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec
   md_ctl_dev* c = (md_ctl_dev*)ctl;
   if (prec == MD_FP32) {
     MD_DISPATCH_LANES(nl->lanes, (launch_lj<float, L_>(*b, *p, pos, *nl, force, vel, inv_mass,
-                                                       half_dt, ev, ev_cap, partial, c, st)));
+                                                       half_dt, (long long*)ev, ev_cap, partial, c, st)));
   } else {
     MD_DISPATCH_LANES(nl->lanes, (launch_lj<double, L_>(*b, *p, pos, *nl, force, vel, inv_mass,
-                                                        half_dt, ev, ev_cap, partial, c, st)));
+                                                        half_dt, (long long*)ev, ev_cap, partial, c, st)));
   }
   MD_LAUNCH_CHECK();
   return MD_OK;

@@ -21,14 +21,28 @@
 
 struct md_ctl_dev {
   int rebuild;     // 1: the MD_IF_FLAGGED rebuild kernels do their work
-  int step;        // completed kick-drift steps
+  int step;        // current step (advanced by the force pass that follows a kick-drift)
   int flags;       // sticky MD_FLAG_* bits
   int n_rebuilds;
   int max_nneigh;
-  int n_dmax;      // number of valid entries in dmax[]
-  int pad[2];
+  int n_dmax;      // valid entries in dmax[] (0 right after a rebuild)
+  int step_next;   // step + 1, published by the kick-drift
+  int pad;
+  double thr2;     // (half skin)^2 of the last kick-drift; < 0: no criterion
+  double pad2;
   double dmax[MD_MAX_ATOM_BLOCKS];  // per-block max |x - x_ref|^2 of the last drift
 };
+
+// Largest per-block displacement of the last drift above the threshold?  Read
+// by every block that needs it (each block reduces the <= 4096 maxima itself).
+__device__ __forceinline__ bool md_displacement_exceeded(const md_ctl_dev* ctl) {
+  const double thr2 = ctl->thr2;
+  const int n = ctl->n_dmax;
+  int over = 0;
+  if (thr2 >= 0.0)
+    for (int k = threadIdx.x; k < n; k += blockDim.x) over |= ctl->dmax[k] > thr2;
+  return __syncthreads_or(over) != 0;
+}
 
 // Offsets of the workspace regions (bytes, 256-aligned).
 struct md_ws_layout {
@@ -50,6 +64,11 @@ static inline md_ws_layout md_ws_plan(const md_batch* b) {
   L.total = o;
   return L;
 }
+
+// nneigh[i] = list length | MD_NN_IMG when the atom's cell stencil crosses a
+// periodic boundary (only then do the force passes apply the minimum image).
+#define MD_NN_IMG (1 << 30)
+#define MD_NN_MASK (MD_NN_IMG - 1)
 
 static inline int md_npad(int n) { return (n + 63) & ~63; }
 
@@ -101,29 +120,56 @@ __device__ __forceinline__ T md_group_sum(T v) {
   return v;
 }
 
-// Deterministic block sum of NV doubles: wave butterflies, then wave 0 adds the
-// per-wave results in wave order.  Result valid in thread 0.  `sh` must hold
-// NV * (blockDim / 64) doubles.
+// Deterministic block sum of NV doubles: wave butterflies, then wave 0 combines
+// the per-wave results with a second butterfly (fixed order).  Result valid in
+// thread 0.  `sh` must hold NV * (blockDim / 64) doubles; blockDim <= 4096.
 template <int NV>
 __device__ __forceinline__ void md_block_sum(double (&v)[NV], double* sh) {
   const int lane = threadIdx.x & (MD_WAVE - 1), wid = threadIdx.x / MD_WAVE;
   const int nw = blockDim.x / MD_WAVE;
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = md_wave_sum(v[k]);
+  if (nw == 1) return;
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) sh[wid * NV + k] = v[k];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (wid == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = sh[k];
-      for (int w = 1; w < nw; ++w) s += sh[w * NV + k];
-      v[k] = s;
-    }
+    for (int k = 0; k < NV; ++k) v[k] = md_wave_sum(lane < nw ? sh[lane * NV + k] : 0.0);
   }
   __syncthreads();
+}
+
+// Per-group sums for blocks that process G groups of W wavefronts each (one work
+// tile per group): wave butterflies, then thread g*NV + k adds the W wave results
+// of group g in wave order.  Returns true in the threads holding out[g*NV + k] in
+// `res`.  `sh` must hold NV * (blockDim / 64) doubles.
+template <int NV>
+__device__ __forceinline__ bool md_group_waves_sum(double (&v)[NV], int waves_per_group,
+                                                   double* sh, double& res, int& g, int& k) {
+  const int lane = threadIdx.x & (MD_WAVE - 1), wid = threadIdx.x / MD_WAVE;
+  const int nw = blockDim.x / MD_WAVE;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = md_wave_sum(v[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[wid * NV + q] = v[q];
+  }
+  __syncthreads();
+  const int ng = nw / waves_per_group;
+  const int tid = threadIdx.x;
+  bool have = tid < ng * NV;
+  if (have) {
+    g = tid / NV;
+    k = tid % NV;
+    double s = sh[(g * waves_per_group) * NV + k];
+    for (int w = 1; w < waves_per_group; ++w) s += sh[(g * waves_per_group + w) * NV + k];
+    res = s;
+  }
+  __syncthreads();
+  return have;
 }
 
 // Cross-block results are never combined inside a kernel: on MI355X each of the

@@ -45,7 +45,12 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double inv_w, int
 __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_bin_count(md_batch b, int mode, double4* pos,
                                                              int* cell_of, int* counts,
                                                              md_ctl_dev* ctl) {
-  if (skip_rebuild(mode, ctl)) return;
+  // The rebuild decision: every block reduces the displacement maxima of the last
+  // drift itself (no cross-block communication); block 0 publishes it for the
+  // other rebuild kernels of this call.
+  const bool go = mode == MD_ALWAYS || md_displacement_exceeded(ctl);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->rebuild = go ? 1 : 0;
+  if (!go) return;
   int bad = 0;
   FOR_ATOMS(b, i, T, {
     const md_domain& D = b.domains[T.rep];
@@ -150,9 +155,10 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_bin_gather(
 // 5. copy the sorted records back and take them as the displacement reference.
 __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_bin_copyback(
     md_batch b, int mode, const double4* pos_s, const double* vel_s, const int* id_s,
-    double4* pos, double* vel, int* id, double* pos_ref, const md_ctl_dev* ctl) {
+    double4* pos, double* vel, int* id, double* pos_ref, md_ctl_dev* ctl) {
   if (skip_rebuild(mode, ctl)) return;
   const int n = b.n_atoms;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->n_dmax = 0;  // displacements now measured afresh
   FOR_ATOMS(b, i, T, {
     const double4 p = pos_s[i];
     pos[i] = p;
@@ -190,91 +196,153 @@ __device__ __forceinline__ int stencil_axis(int c, int nc, int periodic, int* ou
   return m;
 }
 
-// Candidates j of atom i in [jb, je) (cell order), 4 in flight; appends the
-// neighbours in candidate order.
-struct BuildCtx {
-  double4 p;
+// Verlet list with BL lanes per atom.  The atom's candidates are the atoms of the
+// (de-duplicated) 3x3x3 cell block, taken as up to 27 index ranges (three
+// z-neighbouring cells that do not wrap form one range).  The atom's BL lanes
+// walk each range in lock step, BL consecutive candidates per round; a wavefront
+// ballot of the accepted flags gives every accepted candidate its slot (the
+// number of accepted candidates before it), so one pass writes the list in
+// candidate order: deterministic, and neighbouring atoms get similar lists.
+// The tile's 64 lists are assembled in LDS and written out row by row, each
+// row of the strided layout being one contiguous segment (coalesced stores).
+constexpr int BL = 8;
+constexpr int BU = 4;                  // candidate rounds per trip (loads in flight)
+constexpr int BUILD_BLOCK = 64 * BL;  // one work tile per block
+constexpr int MAX_STAGED = 192;       // 64 lists of this length + ranges fit 64 KB of LDS
+
+
+// r^2 < r_ns^2 for the pair, with the minimum image when IMG.  Without it the
+// result is identical: for an atom whose cell block does not wrap, |d| < L/2 and
+// d - L rint(d / L) = d - 0 = d exactly.
+template <bool IMG>
+__device__ __forceinline__ bool accept(const double4& p, const double4& q, const double* len,
+                                       const double* inv, const int* per, double rns2) {
+  double dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+  if (IMG) {
+    if (per[0]) dx = dx - len[0] * rint(dx * inv[0]);
+    if (per[1]) dy = dy - len[1] * rint(dy * inv[1]);
+    if (per[2]) dz = dz - len[2] * rint(dz * inv[2]);
+  }
+  const double r2 = (dx * dx + dy * dy) + dz * dz;
+  return r2 < rns2;
+}
+
+template <bool STAGE>
+__global__ __launch_bounds__(BUILD_BLOCK) void k_build(md_batch b, int mode,
+                                                       const double4* __restrict__ pos,
+                                                       const int* __restrict__ cell_start,
+                                                       int* neigh, int* nneigh, int max_neigh,
+                                                       int lanes_log2, int npad, double rns2,
+                                                       md_ctl_dev* ctl) {
+  if (skip_rebuild(mode, ctl)) return;
+  const int t = md_remap_block(b.n_tiles);
+  if (t >= b.n_tiles) return;
+  const md_tile T = b.tiles[t];
+  const md_domain& D = b.domains[T.rep];
+  const int a = threadIdx.x / BL, l = threadIdx.x % BL;
+  const bool active = a < T.count;
+  const int i = T.first + (active ? a : 0);
   double len[3], inv[3];
   int per[3];
-  double rns2;
-  int i, cnt, max_neigh, lanes_log2, npad;
-  int* neigh;
-};
-
-__device__ __forceinline__ void scan_range(BuildCtx& c, const double4* __restrict__ pos, int jb,
-                                           int je) {
-  const int lanes = 1 << c.lanes_log2;
-  for (int j0 = jb; j0 < je; j0 += 4) {
-    double4 q[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) q[u] = pos[min(j0 + u, je - 1)];
+  for (int q = 0; q < 3; ++q) {
+    len[q] = D.len[q];
+    inv[q] = D.inv_len[q];
+    per[q] = D.periodic[q];
+  }
+  const double4 p = pos[i];
+  const int cx = cell_coord(p.x, D.lo[0], D.inv_w[0], D.nc[0]);
+  const int cy = cell_coord(p.y, D.lo[1], D.inv_w[1], D.nc[1]);
+  const int cz = cell_coord(p.z, D.lo[2], D.inv_w[2], D.nc[2]);
+  int sx[3], sy[3], sz[3];
+  const int mx = stencil_axis(cx, D.nc[0], D.periodic[0], sx);
+  const int my = stencil_axis(cy, D.nc[1], D.periodic[1], sy);
+  const int mz = stencil_axis(cz, D.nc[2], D.periodic[2], sz);
+  const bool zrun = (mz == 3) && (sz[0] + 1 == sz[1]) && (sz[1] + 1 == sz[2]);
+  // the atom's candidate ranges, shared by its lanes through LDS; the (x, y)
+  // columns of the stencil are spread over the atom's lanes so that their
+  // cell_start lookups are in flight together
+  __shared__ int2 s_rng[64][27];
+  __shared__ int s_nr[64];
+  {
+    const int ncol = mx * my, per_col = zrun ? 1 : mz;
+    for (int c = l; c < ncol; c += BL) {
+      const int ix = c / my, iy = c - ix * my;
+      const int col = D.cell_off + (sx[ix] * D.nc[1] + sy[iy]) * D.nc[2];
+      if (zrun) {
+        s_rng[a][c] = make_int2(cell_start[col + sz[0]], cell_start[col + sz[2] + 1]);
+      } else {
+        for (int iz = 0; iz < mz; ++iz)
+          s_rng[a][c * mz + iz] = make_int2(cell_start[col + sz[iz]], cell_start[col + sz[iz] + 1]);
+      }
+    }
+    if (l == 0) s_nr[a] = active ? ncol * per_col : 0;
+  }
+  __syncthreads();
+  const int nrng = s_nr[a];
+  extern __shared__ int s_list[];  // [64][max_neigh]
+  bool img = false;
+  if (D.periodic[0]) img |= (D.nc[0] < 3) || cx == 0 || cx == D.nc[0] - 1;
+  if (D.periodic[1]) img |= (D.nc[1] < 3) || cy == 0 || cy == D.nc[1] - 1;
+  if (D.periodic[2]) img |= (D.nc[2] < 3) || cz == 0 || cz == D.nc[2] - 1;
+  // the minimum-image test is taken by the whole wavefront when any of its atoms
+  // needs it (for the others it gives the identical result)
+  const bool wimg = __any(img);
+  const int lanes = 1 << lanes_log2;
+  const int gshift = (threadIdx.x & (MD_WAVE - 1)) & ~(BL - 1);  // the atom's lanes in the ballot
+  const unsigned below = (1u << l) - 1u;
+  int total = 0;
+  for (int r = 0; r < nrng; ++r) {
+    const int jb = s_rng[a][r].x, je = s_rng[a][r].y;
+    // BU rounds of BL candidates per trip, their loads issued together
+    for (int j0 = jb; j0 < je; j0 += BL * BU) {
+      double4 q[BU];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = j0 + u;
-      if (j >= je || j == c.i) continue;
-      double dx = q[u].x - c.p.x, dy = q[u].y - c.p.y, dz = q[u].z - c.p.z;
-      if (c.per[0]) dx = dx - c.len[0] * rint(dx * c.inv[0]);
-      if (c.per[1]) dy = dy - c.len[1] * rint(dy * c.inv[1]);
-      if (c.per[2]) dz = dz - c.len[2] * rint(dz * c.inv[2]);
-      const double r2 = (dx * dx + dy * dy) + dz * dz;
-      if (r2 < c.rns2) {
-        if (c.cnt < c.max_neigh)
-          c.neigh[((size_t)(c.cnt >> c.lanes_log2) * c.npad + c.i) * lanes +
-                  (c.cnt & (lanes - 1))] = j;
-        ++c.cnt;
+      for (int u = 0; u < BU; ++u) q[u] = pos[min(j0 + u * BL + l, je - 1)];
+#pragma unroll
+      for (int u = 0; u < BU; ++u) {
+        const int j = j0 + u * BL + l;
+        const bool in = wimg ? accept<true>(p, q[u], len, inv, per, rns2)
+                             : accept<false>(p, q[u], len, inv, per, rns2);
+        const bool ok = (j < je) & (j != i) & in;
+        const unsigned g = (unsigned)(__ballot(ok) >> gshift) & ((1u << BL) - 1u);
+        if (ok) {
+          const int slot = total + __popc(g & below);
+          if (slot < max_neigh) {
+            if (STAGE)
+              s_list[a * max_neigh + slot] = j;
+            else
+              neigh[((size_t)(slot >> lanes_log2) * npad + i) * lanes + (slot & (lanes - 1))] = j;
+          }
+        }
+        total += __popc(g);
       }
     }
   }
-}
-
-__global__ __launch_bounds__(MD_ATOM_BLOCK) void k_build(md_batch b, int mode,
-                                                         const double4* __restrict__ pos,
-                                                         const int* __restrict__ cell_start,
-                                                         int* neigh, int* nneigh, int max_neigh,
-                                                         int lanes_log2, int npad, double rns2,
-                                                         md_ctl_dev* ctl) {
-  if (skip_rebuild(mode, ctl)) return;
-  int wmax = 0, over = 0;
-  FOR_ATOMS(b, i, T, {
-    const md_domain& D = b.domains[T.rep];
-    BuildCtx c;
-    c.p = pos[i];
-_Pragma("unroll")
-    for (int a = 0; a < 3; ++a) {
-      c.len[a] = D.len[a];
-      c.inv[a] = D.inv_len[a];
-      c.per[a] = D.periodic[a];
+  if (STAGE) {
+    // coalesced write-out: row q of the layout holds entries q*lanes .. q*lanes+lanes-1
+    // of every atom; the tile's atoms occupy 64*lanes consecutive ints of each row.
+    __shared__ int s_cnt[64];
+    if (l == 0) s_cnt[a] = active ? min(total, max_neigh) : 0;
+    __syncthreads();
+    int tmax = 0;
+    for (int q = 0; q < 64; ++q) tmax = max(tmax, s_cnt[q]);
+    const int rows = (tmax + lanes - 1) >> lanes_log2;
+    const int span = 64 * lanes;
+    for (int e = threadIdx.x; e < rows * span; e += blockDim.x) {
+      const int q = e / span, w = e - q * span;
+      const int aa = w >> lanes_log2, m = q * lanes + (w & (lanes - 1));
+      if (aa < T.count && m < s_cnt[aa])
+        neigh[((size_t)q * npad + T.first) * lanes + w] = s_list[aa * max_neigh + m];
     }
-    c.rns2 = rns2;
-    c.i = i;
-    c.cnt = 0;
-    c.max_neigh = max_neigh;
-    c.lanes_log2 = lanes_log2;
-    c.npad = npad;
-    c.neigh = neigh;
-    const int cx = cell_coord(c.p.x, D.lo[0], D.inv_w[0], D.nc[0]);
-    const int cy = cell_coord(c.p.y, D.lo[1], D.inv_w[1], D.nc[1]);
-    const int cz = cell_coord(c.p.z, D.lo[2], D.inv_w[2], D.nc[2]);
-    int sx[3], sy[3], sz[3];
-    const int mx = stencil_axis(cx, D.nc[0], D.periodic[0], sx);
-    const int my = stencil_axis(cy, D.nc[1], D.periodic[1], sy);
-    const int mz = stencil_axis(cz, D.nc[2], D.periodic[2], sz);
-    // Three z-neighbouring cells that do not wrap are one contiguous range.
-    const bool zrun = (mz == 3) && (sz[0] + 1 == sz[1]) && (sz[1] + 1 == sz[2]);
-    for (int ix = 0; ix < mx; ++ix)
-      for (int iy = 0; iy < my; ++iy) {
-        const int col = D.cell_off + (sx[ix] * D.nc[1] + sy[iy]) * D.nc[2];
-        if (zrun) {
-          scan_range(c, pos, cell_start[col + sz[0]], cell_start[col + sz[2] + 1]);
-        } else {
-          for (int iz = 0; iz < mz; ++iz)
-            scan_range(c, pos, cell_start[col + sz[iz]], cell_start[col + sz[iz] + 1]);
-        }
-      }
-    nneigh[i] = c.cnt < max_neigh ? c.cnt : max_neigh;
-    over |= c.cnt > max_neigh;
-    wmax = max(wmax, c.cnt);
-  });
+  }
+  int over = 0, wmax = 0;
+  if (active && l == 0) {
+    // img: the stencil crosses a periodic boundary (wrapped cell, or fewer than 3 cells)
+    nneigh[i] = (total < max_neigh ? total : max_neigh) | (img ? MD_NN_IMG : 0);
+    over = total > max_neigh;
+    wmax = total;
+  }
   if (__any(over)) {
     if ((threadIdx.x & (MD_WAVE - 1)) == 0) md_flag(ctl, MD_FLAG_NEIGH_OVERFLOW);
   }
@@ -339,10 +407,20 @@ extern "C" int md_build_neighbors(const md_batch* b, md_rebuild_mode mode, const
   if (lg < 0 || nl->max_neigh < nl->lanes || nl->max_neigh % nl->lanes) return MD_ERR_ARG;
   if (!(b->r_ns > 0.0)) return MD_ERR_ARG;
   if (b->n_atoms == 0) return MD_OK;
-  const dim3 grid(md_atom_grid(b->n_tiles)), block(MD_ATOM_BLOCK);
-  MD_LAUNCH_TIMED(MD_KERNEL_BUILD, k_build, grid, block, 0, (hipStream_t)stream, *b, (int)mode,
-                  (const double4*)pos, cell_start, nl->neigh, nl->nneigh, nl->max_neigh, lg,
-                  md_npad(b->n_atoms), b->r_ns * b->r_ns, (md_ctl_dev*)ctl);
+  const dim3 grid(md_grid_blocks(b->n_tiles)), block(BUILD_BLOCK);
+  // Lists are staged in LDS (coalesced write-out) when the tile's 64 lists fit
+  // beside the static ranges within 64 KB; longer lists are stored directly.
+  const size_t lds = (size_t)64 * nl->max_neigh * sizeof(int);
+  if (nl->max_neigh <= MAX_STAGED)
+    MD_LAUNCH_TIMED(MD_KERNEL_BUILD, k_build<true>, grid, block, lds, (hipStream_t)stream, *b,
+                    (int)mode, (const double4*)pos, cell_start, nl->neigh, nl->nneigh,
+                    nl->max_neigh, lg, md_npad(b->n_atoms), b->r_ns * b->r_ns,
+                    (md_ctl_dev*)ctl);
+  else
+    MD_LAUNCH_TIMED(MD_KERNEL_BUILD, k_build<false>, grid, block, 0, (hipStream_t)stream, *b,
+                    (int)mode, (const double4*)pos, cell_start, nl->neigh, nl->nneigh,
+                    nl->max_neigh, lg, md_npad(b->n_atoms), b->r_ns * b->r_ns,
+                    (md_ctl_dev*)ctl);
   MD_LAUNCH_CHECK();
   return MD_OK;
 }

@@ -16,7 +16,7 @@ struct Walls {
 template <typename R>
 __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_kick_drift(
     md_batch b, double dt, double half_dt, double4* pos, double* vel, const R* force,
-    double inv_mass, Walls w, const double* pos_ref, md_ctl_dev* ctl) {
+    double inv_mass, Walls w, const double* pos_ref, double thr2, md_ctl_dev* ctl) {
   __shared__ double sh[MD_ATOM_BLOCK / MD_WAVE];
   const int nlb = (b.n_tiles + 3) / 4;
   const int lane = threadIdx.x & (MD_WAVE - 1);
@@ -73,23 +73,11 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_kick_drift(
     double m = sh[0];
     for (int k = 1; k < MD_ATOM_BLOCK / MD_WAVE; ++k) m = fmax(m, sh[k]);
     ctl->dmax[blockIdx.x] = m;
-    if (blockIdx.x == 0) ctl->n_dmax = gridDim.x;
-  }
-}
-
-// One block: the rebuild decision for the next md_bin_cells, and the step counter.
-__global__ __launch_bounds__(256) void k_verlet_finish(md_ctl_dev* ctl, double thr2) {
-  __shared__ double sh[4];
-  double m = 0.0;
-  for (int k = threadIdx.x; k < ctl->n_dmax; k += blockDim.x) m = fmax(m, ctl->dmax[k]);
-#pragma unroll
-  for (int o = MD_WAVE / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, MD_WAVE));
-  if ((threadIdx.x & (MD_WAVE - 1)) == 0) sh[threadIdx.x / MD_WAVE] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    m = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
-    ctl->rebuild = (thr2 < 0.0) ? 0 : (m > thr2 ? 1 : 0);
-    ctl->step = ctl->step + 1;
+    if (blockIdx.x == 0) {  // fields no block of this kernel reads
+      ctl->n_dmax = gridDim.x;
+      ctl->thr2 = thr2;
+      ctl->step_next = ctl->step + 1;
+    }
   }
 }
 
@@ -149,12 +137,10 @@ extern "C" int md_verlet_step(const md_batch* b, md_verlet_phase phase, double d
   md_ctl_dev* c = (md_ctl_dev*)ctl;
   if (prec == MD_FP32)
     MD_LAUNCH_TIMED(MD_KERNEL_KICK_DRIFT, k_kick_drift<float>, grid, block, 0, st, *b, dt,
-                    0.5 * dt, (double4*)pos, vel, (const float*)force, inv_mass, w, pos_ref, c);
+                    0.5 * dt, (double4*)pos, vel, (const float*)force, inv_mass, w, pos_ref, thr2, c);
   else
     MD_LAUNCH_TIMED(MD_KERNEL_KICK_DRIFT, k_kick_drift<double>, grid, block, 0, st, *b, dt,
-                    0.5 * dt, (double4*)pos, vel, (const double*)force, inv_mass, w, pos_ref, c);
-  MD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_verlet_finish, dim3(1), dim3(256), 0, st, c, thr2);
+                    0.5 * dt, (double4*)pos, vel, (const double*)force, inv_mass, w, pos_ref, thr2, c);
   MD_LAUNCH_CHECK();
   return MD_OK;
 }

@@ -20,6 +20,16 @@ from ._native import MDError, check  # noqa: F401
 ACCEL = 9648.5332157  # 1 eV/(u angstrom) in angstrom/ps^2 (unit conversion for callers)
 
 
+def ev_buffer(ev_cap, n_rep, device="cuda"):
+    """Per-step records [ev_cap, n_rep, 8] (int64 fixed point, md.h MD_EV_SCALE)."""
+    return torch.zeros((ev_cap, n_rep, N.MD_EV_LEN), dtype=torch.int64, device=device)
+
+
+def ev_values(ev):
+    """Records in eV: {E_pot, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz, K} as float64 numpy."""
+    return ev.cpu().numpy().astype(np.float64) / N.MD_EV_SCALE
+
+
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
@@ -98,9 +108,13 @@ class NeighborList:
         self.nneigh = torch.zeros(max(1, n_atoms), dtype=torch.int32, device=device)
         self.c = N.NList(self.neigh.data_ptr(), self.nneigh.data_ptr(), max_neigh, lanes)
 
+    def lengths(self):
+        """List lengths (the image flag masked off)."""
+        return self.nneigh[:self.n] & (N.MD_NN_IMG - 1)
+
     def host_lists(self):
         """Per atom (current order) the array of neighbour indices (current order)."""
-        nn = self.nneigh.cpu().numpy()[:self.n]
+        nn = self.nneigh.cpu().numpy()[:self.n] & (N.MD_NN_IMG - 1)
         raw = self.neigh.cpu().numpy().reshape(self.max_neigh // self.lanes, self.npad, self.lanes)
         out = []
         for i in range(self.n):

@@ -1,12 +1,19 @@
 """NVE driver: the sequence of library calls that makes one velocity-Verlet step
-(Sec. 1.5) with predicated neighbour-list rebuilds (Sec. 1.4), optionally
-captured once into a HIP graph and replayed.
+(Sec. 1.5) with neighbour-list rebuilds (Sec. 1.4), optionally captured once into
+a HIP graph and replayed.
 
 One step, all on one stream, no host synchronisation:
-  md_verlet_step(KICK_DRIFT)          v += dt/2 f/m; x += dt v; walls; displacement check
-  md_bin_cells(IF_FLAGGED)            wrap + counting sort, only if an atom moved > skin/2
-  md_build_neighbors(IF_FLAGGED)      Verlet list, same predicate
+  md_verlet_step(KICK_DRIFT)          v += dt/2 f/m; x += dt v; walls; displacements
+  md_bin_cells, md_build_neighbors    rebuild (policy below)
   md_eam_forces / md_lj_forces        forces, energy, virial, trailing kick v += dt/2 f/m
+
+Rebuild policies (both in the paper):
+  rebuild_every = 0: on the threshold (Sec. 1.4) -- the rebuild kernels run every
+      step in MD_IF_FLAGGED mode and do work only when an atom moved > skin/2;
+  rebuild_every = k: every k steps (the benchmark of Sec. 1.7) -- the rebuild
+      kernels are launched only on those steps; the force pass verifies the
+      half-skin criterion on every step (MD_ERR_STALE_LIST if violated), so a run
+      that ends with clear flags used valid lists throughout.
 """
 from __future__ import annotations
 
@@ -19,8 +26,10 @@ from . import md
 
 class Simulation:
     def __init__(self, system, precision=N.MD_FP64, lanes=4, max_neigh=128, ev_cap=1024,
-                 device="cuda", table=None):
+                 device="cuda", table=None, rebuild_every=0):
         self.sys = system
+        self.rebuild_every = int(rebuild_every)
+        self.n_steps = 0
         self.precision = precision
         r_cut = system.lj.r_cut if system.potential == "lj" else system.eam.r_cut
         self.r_ns = r_cut + system.skin
@@ -32,7 +41,7 @@ class Simulation:
         self.half_skin = 0.5 * system.skin
         self.walls = md.walls_params(system.walls)
         self.ev_cap = ev_cap
-        self.ev = torch.zeros((ev_cap, 1, N.MD_EV_LEN), dtype=torch.float64, device=device)
+        self.ev = md.ev_buffer(ev_cap, 1, device)
         if system.potential == "lj":
             self.lj = md.lj_params(system.lj.eps, system.lj.sigma, system.lj.r_cut)
             self.pot = None
@@ -61,16 +70,41 @@ class Simulation:
         self.forces(kick=False)
         return self
 
+    def rebuild(self):
+        """Rebuild the cell order and the list now (e.g. when switching rebuild policy)."""
+        md.md_bin_cells(self.state, N.MD_ALWAYS)
+        md.md_build_neighbors(self.state, self.nl, N.MD_ALWAYS)
+
+    def set_rebuild_every(self, k):
+        """Switch the rebuild policy; rebuilds now so that the next period starts fresh."""
+        self.rebuild_every = int(k)
+        self.graph = None
+        self.rebuild()
+        if k > 0:
+            self.n_steps -= self.n_steps % k
+
     def step(self, ev=True):
         st = self.state
         md.md_verlet_step(st, N.MD_KICK_DRIFT, self.dt, self.inv_mass, self.walls, self.half_skin)
-        md.md_bin_cells(st, N.MD_IF_FLAGGED)
-        md.md_build_neighbors(st, self.nl, N.MD_IF_FLAGGED)
+        k = self.rebuild_every
+        if k <= 0:
+            md.md_bin_cells(st, N.MD_IF_FLAGGED)
+            md.md_build_neighbors(st, self.nl, N.MD_IF_FLAGGED)
+        elif (self.n_steps + 1) % k == 0:
+            md.md_bin_cells(st, N.MD_ALWAYS)
+            md.md_build_neighbors(st, self.nl, N.MD_ALWAYS)
         self.forces(kick=True, ev=ev)
+        self.n_steps += 1
 
     # -- graphs ---------------------------------------------------------------
     def capture(self, steps, ev=True):
-        """Capture `steps` consecutive steps into one graph."""
+        """Capture `steps` consecutive steps into one graph (for rebuild_every = k the graph
+        must start at a multiple of k and span a multiple of k steps)."""
+        k = self.rebuild_every
+        if k > 0 and (steps % k or self.n_steps % k):
+            raise ValueError("graph of %d steps at step %d does not align with rebuilds every %d"
+                             % (steps, self.n_steps, k))
+        n0 = self.n_steps
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         g = torch.cuda.CUDAGraph()
@@ -78,15 +112,23 @@ class Simulation:
             for _ in range(steps):
                 self.step(ev)
         torch.cuda.current_stream().wait_stream(s)
+        self.n_steps = n0  # capture recorded the steps; replays perform them
         self.graph, self.graph_steps = g, steps
         return g
 
     def run(self, n_steps, graph_steps=0, ev=True):
+        k = self.rebuild_every
+        if k > 0 and graph_steps:
+            graph_steps = max(k, graph_steps // k * k)
+            while n_steps > 0 and self.n_steps % k:  # align to the rebuild period
+                self.step(ev)
+                n_steps -= 1
         if graph_steps and n_steps >= graph_steps:
             if self.graph is None or self.graph_steps != graph_steps:
                 self.capture(graph_steps, ev)
             for _ in range(n_steps // graph_steps):
                 self.graph.replay()
+                self.n_steps += graph_steps
             rest = n_steps % graph_steps
         else:
             rest = n_steps
@@ -96,6 +138,6 @@ class Simulation:
     # -- results --------------------------------------------------------------
     def energies(self, steps):
         """(step, PE, KE, W[6]) for the given step numbers (must be within the last ev_cap)."""
-        ev = self.ev.cpu().numpy()[:, 0, :]
+        ev = md.ev_values(self.ev)[:, 0, :]
         rows = [ev[s % self.ev_cap] for s in steps]
         return np.array(rows)

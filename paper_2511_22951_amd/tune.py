@@ -75,7 +75,7 @@ def best_lanes(system, prec, candidates=CANDIDATES, samples=10, use_cache=True):
     for lanes in candidates:
         sim = Simulation(system, precision=prec, lanes=lanes, ev_cap=4).setup()
         if key is None:
-            mean_nb = sim.nl.nneigh[:sim.plan.n_atoms].double().mean().item()
+            mean_nb = sim.nl.lengths().double().mean().item()
             key = _key(name, system.potential, prec, sim.plan.n_atoms, mean_nb)
             if key in cache:
                 return int(cache[key]["lanes"])

@@ -34,3 +34,15 @@ def rel_fro(a, b):
 
 def oracle_eam(pos, box, table):
     return core.eam(pos, box, core.EAMPotential.from_table(table))
+
+
+def md_ev(n_rep=1, cap=1):
+    """A per-step record buffer for cap steps of n_rep boxes (int64 fixed point)."""
+    from paper_2511_22951_amd import md
+    return md.ev_buffer(cap, n_rep)
+
+
+def evv(ev):
+    """Records in eV as float64 numpy."""
+    from paper_2511_22951_amd import md
+    return md.ev_values(ev)

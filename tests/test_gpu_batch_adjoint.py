@@ -10,6 +10,8 @@ import numpy as np
 import pytest
 import torch
 
+from tests.gpu_util import evv, md_ev
+
 import mdinputs as mi
 from oracle import adjoint as oadj
 from oracle import core
@@ -43,10 +45,10 @@ def test_batched_replicas_match_closed_form_and_single_calls(md):
     tab = mi.tabulate_eam(mi.EAM_CU)
     pot = md.EAMPotential.from_table(tab)
     plan, st, nl = _batch(md, reps)
-    ev = torch.zeros((1, len(reps), 8), dtype=torch.float64, device="cuda")
+    ev = md_ev(len(reps))
     md.md_eam_forces(st, pot, nl, ev=ev)
     st.check_flags()
-    e = ev.cpu().numpy()[0]
+    e = evv(ev)[0]
     assert np.max(np.abs(st.forces())) < 1e-10
     opot = core.EAMPotential.from_table(tab)
     sets = neighbor_sets_by_id(st, nl)
@@ -63,9 +65,9 @@ def test_batched_replicas_match_closed_form_and_single_calls(md):
             assert np.array_equal(sets[off + i] - off, want[i])
         # the same box alone
         p1, s1, n1 = _batch(md, [rep])
-        ev1 = torch.zeros((1, 1, 8), dtype=torch.float64, device="cuda")
+        ev1 = md_ev(1)
         md.md_eam_forces(s1, pot, n1, ev=ev1)
-        assert abs(ev1.cpu().numpy()[0, 0, 0] - e[r, 0]) < 1e-12 * abs(e[r, 0])
+        assert abs(evv(ev1)[0, 0, 0] - e[r, 0]) < 1e-12 * abs(e[r, 0])
         off += n
 
 
@@ -74,10 +76,10 @@ def test_cold_curve_64_replicas(md, prec):
     reps = mi.cold_curve_replicas()
     pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
     plan, st, nl = _batch(md, reps, prec=prec)
-    ev = torch.zeros((1, len(reps), 8), dtype=torch.float64, device="cuda")
+    ev = md_ev(len(reps))
     md.md_eam_forces(st, pot, nl, ev=ev)
     st.check_flags()
-    e = ev.cpu().numpy()[0]
+    e = evv(ev)[0]
     tol = 1e-9 if prec == 0 else 1e-6
     for r, rep in enumerate(reps):
         e_cf, _ = ls.eam_per_atom(rep.a, mi.EAM_CU)
@@ -96,7 +98,7 @@ def test_batched_graph_replay_equals_eager(md):
     reps = mi.cold_curve_replicas(n_rep=16, seed=33, n_min=4, n_max=6)
     pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
     plan, st, nl = _batch(md, reps)
-    ev = torch.zeros((1, len(reps), 8), dtype=torch.float64, device="cuda")
+    ev = md_ev(len(reps))
     table = pot.table(0)
     md.md_eam_forces(st, pot, nl, table=table, ev=ev)
     torch.cuda.synchronize()

@@ -10,6 +10,8 @@ import numpy as np
 import pytest
 import torch
 
+from tests.gpu_util import evv, md_ev
+
 import mdinputs as mi
 from oracle import core, integrate
 from oracle import spline as osp
@@ -105,11 +107,11 @@ def test_lj_fp64_matches_oracle(mdmod, cells, lanes):
     p = mi.LJ_AR
     pos, box = displaced(cells, 5.26, 0.15, seed=11)
     plan, st, nl = _setup(mdmod, pos, box, p.r_cut + 0.3, lanes=lanes)
-    ev = torch.zeros((1, 1, 8), dtype=torch.float64, device="cuda")
+    ev = md_ev(1)
     mdmod.md_lj_forces(st, mdmod.lj_params(p.eps, p.sigma, p.r_cut), nl, ev=ev)
     r = core.lj(pos, box, p.eps, p.sigma, p.r_cut)
     assert rel_fro(st.forces(), r.force) < 1e-12
-    e = ev.cpu().numpy()[0, 0]
+    e = evv(ev)[0, 0]
     assert abs(e[0] - r.energy) < 1e-12 * abs(r.energy)
     assert np.max(np.abs(e[1:7] - r.virial)) < 1e-11 * np.max(np.abs(r.virial))
 
@@ -118,11 +120,11 @@ def test_lj_fp32_within_tolerance(mdmod):
     p = mi.LJ_AR
     pos, box = displaced(5, 5.26, 0.15, seed=12)
     plan, st, nl = _setup(mdmod, pos, box, p.r_cut + 0.3, prec=1)
-    ev = torch.zeros((1, 1, 8), dtype=torch.float64, device="cuda")
+    ev = md_ev(1)
     mdmod.md_lj_forces(st, mdmod.lj_params(p.eps, p.sigma, p.r_cut), nl, ev=ev)
     r = core.lj(pos, box, p.eps, p.sigma, p.r_cut)
     assert rel_fro(st.forces(), r.force) < 1e-5
-    assert abs(ev.cpu().numpy()[0, 0, 0] - r.energy) / len(pos) < 1e-6
+    assert abs(evv(ev)[0, 0, 0] - r.energy) / len(pos) < 1e-6
 
 
 @pytest.mark.parametrize("prec,lanes", [(0, 4), (0, 1), (0, 16), (1, 4), (1, 8)])
@@ -131,12 +133,12 @@ def test_eam_matches_oracle(mdmod, prec, lanes):
     pos, box = displaced(6, 3.615, 0.08, seed=13)
     plan, st, nl = _setup(mdmod, pos, box, 5.8, lanes=lanes, prec=prec)
     pot = mdmod.EAMPotential.from_table(tab)
-    ev = torch.zeros((1, 1, 8), dtype=torch.float64, device="cuda")
+    ev = md_ev(1)
     saved = torch.zeros((3, len(pos)), dtype=torch.float64, device="cuda")
     mdmod.md_eam_forces(st, pot, nl, saved=saved, ev=ev)
     st.check_flags()
     r = core.eam(pos, box, core.EAMPotential.from_table(tab))
-    e = ev.cpu().numpy()[0, 0]
+    e = evv(ev)[0, 0]
     order = st._order()
     rb = saved.cpu().numpy()[0][order]
     if prec == 0:
@@ -229,3 +231,36 @@ def test_piston_walls_match_oracle(mdmod):
     per = np.array(s.box.periodic, bool)
     d[:, per] -= L[per] * np.rint(d[:, per] / L[per])
     assert np.max(np.abs(d)) < 1e-9
+
+
+def test_fixed_interval_rebuilds_match_oracle(mdmod):
+    """Rebuilds every 10 steps (the interval of the paper's benchmark) with the half-skin
+    criterion verified on the device: LJ argon follows the oracle for 100 steps, graph
+    replay included, and the flags stay clear."""
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.lj_argon()
+    sim = Simulation(s, precision=0, lanes=4, rebuild_every=10).setup()
+    sim.run(100, graph_steps=20)
+    info = sim.state.check_flags()
+    assert info["step"] == 100 and info["n_rebuilds"] == 11
+    x, v, f, hist = integrate.run_nve(s.pos, s.vel, s.box, s.mass, s.dt_ps, 100,
+                                      integrate.lj_force_fn(s.box, s.lj))
+    d = sim.state.positions() - x
+    L = np.array(s.box.len)
+    d -= L * np.rint(d / L)
+    assert np.max(np.abs(d)) < 1e-9
+    e = sim.energies(range(101))
+    assert np.max(np.abs(e[:, 0] - hist[:, 1])) < 1e-10 * abs(hist[0, 1])
+
+
+def test_stale_list_is_detected(mdmod):
+    """Without rebuilds a hot system soon moves atoms by more than half the skin: the force
+    pass reports MD_ERR_STALE_LIST."""
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.lj_argon()
+    s.vel = s.vel * 4.0
+    sim = Simulation(s, precision=0, lanes=4, rebuild_every=100000).setup()
+    sim.run(40)
+    with pytest.raises(mdmod.MDError) as e:
+        sim.state.check_flags()
+    assert e.value.status == -9
