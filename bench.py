@@ -59,6 +59,38 @@ def algorithmic_force_bytes(n_atoms, mean_neigh, force_bytes):
     return n_atoms * (4.0 + 4.0 * mean_neigh + 32.0 + 3.0 * force_bytes + 48.0)
 
 
+FORCE_SOURCES = ("paper_2511_22951_amd/csrc/md_force.hip", "paper_2511_22951_amd/csrc/md_internal.h",
+                 "paper_2511_22951_amd/csrc/md_tables.h", "include/md.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eam_cu131k_hbm_traffic.txt")
+
+
+def measured_traffic(prec_name, lanes):
+    """HBM bytes per force-pass launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy calibration), or None when the summary was taken for
+    another configuration or the force-pass sources have changed since."""
+    import hashlib
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+        for line in text.splitlines():
+            if " = " in line:
+                k, v = line.split(" = ", 1)
+                kv[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for name in FORCE_SOURCES:
+            with open(os.path.join(ROOT, name), "rb") as f:
+                h.update(f.read())
+    except OSError:
+        return None
+    if kv.get("source_sha256") != h.hexdigest():
+        return None
+    if (kv.get("precision") != prec_name or kv.get("lanes") != str(lanes)
+            or "k_eam_force_traffic_bytes" not in kv):
+        return None
+    return float(kv["k_eam_force_traffic_bytes"])
+
+
 def time_kernel(md_native, kernel, run_once, samples):
     """Mean duration (ms) of one kernel over `samples` launches, each inside run_once()."""
     L = md_native.lib()
@@ -233,7 +265,8 @@ def main():
                    "n_atoms": n, "precision": head, "lanes_per_atom": R["lanes"],
                    "graph_steps": args.graph_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(head, R["lanes"]),
                      "kernel": "k_eam_force", "kernel_us": kt_force * 1e6,
                      "bytes_per_launch": bytes_force},
         "cpu_baseline": cpu,
