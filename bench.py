@@ -36,7 +36,8 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 1000; 5000 for al_shock)")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--graph-steps", type=int, default=50)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: autotune)")
@@ -46,6 +47,11 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device a few times (the known-size "
                          "transfer that scales the FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--workload", choices=["cu131k", "al_shock", "cold_curve", "force_matching"],
+                    default="cu131k",
+                    help="cu131k: the headline EAM Cu NVE run; the others are the secondary "
+                         "measurements (640k-atom Al shock, 64 batched cold-curve replicas, "
+                         "force-matching epochs)")
     ap.add_argument("--rebuild-every", type=int, default=-1,
                     help="rebuild period k (0: on the half-skin threshold every step; "
                          "-1: k chosen from the warm-up's rebuild intervals)")
@@ -212,6 +218,12 @@ def main():
         print("bench.py: this build targets one GPU; --gpus %d is not supported (run with "
               "--gpus 1)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "cu131k" and args.steps is None:
+        args.steps = 1000
+    if args.workload != "cu131k":
+        {"al_shock": bench_al_shock, "cold_curve": bench_cold_curve,
+         "force_matching": bench_force_matching}[args.workload](args)
+        return
     import torch
     import mdinputs as mi
     from paper_2511_22951_amd import _native as N
@@ -291,6 +303,281 @@ def main():
     if e_or is not None:
         paths["oracle_e0_per_atom"] = e_or
     out["paths"] = paths
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Secondary measurements (each prints its own JSON line)
+# ---------------------------------------------------------------------------
+def _gpu_time(fn, reps):
+    """Wall time (ms) of `reps` calls of fn() on the current stream, events on that stream."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def _replay_graph(fn, warm=2):
+    """Capture fn() once into a HIP graph (after `warm` eager calls) and return replay()."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    return g.replay, g
+
+
+def bench_al_shock(args):
+    """640,000-atom Al shock (fcc 20x20x400, piston 1 km/s, top wall), FP32-mixed forces,
+    rebuilds on the half-skin threshold (predicated rebuild kernels every step)."""
+    import torch
+    import mdinputs as mi
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    N.lib()
+    system = mi.eam_aluminum_shock()
+    n = system.pos.shape[0]
+    steps = args.steps or system.n_steps
+    lanes = args.lanes or autotune_lanes(system, N.MD_FP32)
+    cap = args.warmup + steps + args.kernel_samples + 8
+    sim = Simulation(system, precision=N.MD_FP32, lanes=lanes, max_neigh=160, ev_cap=cap,
+                     rebuild_every=0).setup()
+    sim.run(args.warmup, graph_steps=args.graph_steps)
+    torch.cuda.synchronize()
+    st0 = sim.state.read_flags()[1]
+    ms = _gpu_time(lambda: sim.run(steps, graph_steps=args.graph_steps), 1)
+    status, info = sim.state.read_flags()
+    N.check(status, "device flags after the timed run")
+    kt = {}
+    for kname in ("eam_force", "eam_density", "kick_drift"):
+        kt[kname] = time_kernel(N, kname, lambda: sim.step(), args.kernel_samples)[0]
+    nn = sim.nl.lengths().double()
+    zc = sim.state.positions()[:, 2]
+    kt_force = kt["eam_force"] * 1e-3
+    bytes_force = algorithmic_force_bytes(n, nn.mean().item(), 4)
+    achieved = bytes_force / kt_force / 1e9
+    out = {
+        "metric": "atom-steps/s (EAM Al shock, FP32-mixed forces, FP64 integration)",
+        "value": n * steps / (ms * 1e-3), "unit": "atom-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "EAM Al fcc 20x20x400 = 640000 atoms, a 4.05, 300 K, piston "
+                               "1 km/s at z = 0, top wall, periodic x/y, dt 1 fs, skin 0.3, "
+                               "half-skin rebuilds", "n_atoms": n, "lanes_per_atom": lanes,
+                   "graph_steps": args.graph_steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_eam_force",
+                     "kernel_us": kt_force * 1e6, "bytes_per_launch": bytes_force},
+        "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"],
+        "neighbours": {"mean": nn.mean().item(), "max": int(nn.max().item()),
+                       "min": int(nn.min().item())},
+        "piston_z_end": float(system.walls["piston_v"] * info["step"] * system.dt_ps),
+        "atoms_min_z": float(zc.min()),
+        "kernel_us": {k: 1e3 * v for k, v in kt.items()},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _static_batch(reps, prec, lanes, max_neigh=128):
+    from paper_2511_22951_amd import md
+    plan = md.Plan([r.box for r in reps], [len(r.pos) for r in reps], 5.8)
+    st = md.State(plan, np.concatenate([r.pos for r in reps]), None, prec)
+    nl = md.NeighborList(plan.n_atoms, max_neigh, lanes)
+    md.md_bin_cells(st)
+    md.md_build_neighbors(st, nl)
+    return plan, st, nl
+
+
+def bench_cold_curve(args):
+    """64 perfect Cu replicas (4^3..12^3 cells, a = 3.30..4.20): energy, forces and virial of
+    every replica per evaluation.  Batched (one launch per pass over all replicas, HIP graph)
+    against a per-replica loop (64 launches per pass, also in a graph); FP32 and FP64."""
+    import torch
+    import mdinputs as mi
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd import md, tune
+    N.lib()
+    reps = mi.cold_curve_replicas()
+    n_tot = sum(len(r.pos) for r in reps)
+    tab = mi.tabulate_eam(mi.EAM_CU)
+    pot = md.EAMPotential.from_table(tab)
+    reps_per_eval = len(reps)
+    evals = max(20, (args.steps or 1000) // 10)
+    res = {}
+    e_gpu = {}
+    for name, prec in (("fp32", N.MD_FP32), ("fp64", N.MD_FP64)):
+        table = pot.table(prec)
+
+        def batched(lanes):
+            plan, st, nl = _static_batch(reps, prec, lanes)
+            ev = md.ev_buffer(1, len(reps))
+            fn = lambda: md.md_eam_forces(st, pot, nl, table=table, ev=ev)
+            return fn, (plan, st, nl, ev)
+
+        def timed(lanes):
+            fn, keep = batched(lanes)
+            replay, g = _replay_graph(fn)
+            return _gpu_time(replay, 10) / 10
+
+        lanes = args.lanes or tune.pick(("cold_curve64", name), (1, 2, 4, 8), timed)
+        fn, (plan, st, nl, ev) = batched(lanes)
+        replay, g = _replay_graph(fn)
+        t_b = _gpu_time(replay, evals) / evals
+        st.check_flags()
+        e = md.ev_values(ev)[0]
+        e_gpu[name] = (e[:, 0], st)
+        # per-replica loop: one plan/state/list per replica, 64 launches per evaluation
+        singles = []
+        for r in reps:
+            p1, s1, n1 = _static_batch([r], prec, lanes)
+            singles.append((s1, n1, md.ev_buffer(1, 1)))
+
+        def loop():
+            for s1, n1, ev1 in singles:
+                md.md_eam_forces(s1, pot, n1, table=table, ev=ev1)
+
+        replay_l, g_l = _replay_graph(loop)
+        t_l = _gpu_time(replay_l, evals) / evals
+        res[name] = {"ms_per_eval_batched": t_b, "ms_per_eval_loop": t_l,
+                     "replica_evals_per_s": reps_per_eval / (t_b * 1e-3),
+                     "atom_evals_per_s": n_tot / (t_b * 1e-3),
+                     "batched_speedup_over_loop": t_l / t_b, "lanes": lanes,
+                     "max_abs_force": float(np.max(np.abs(st.forces())))}
+        del g, g_l
+    per_atom = np.array([len(r.pos) for r in reps], np.float64)
+    de32 = np.abs(e_gpu["fp32"][0] - e_gpu["fp64"][0]) / per_atom
+    res["fp32"]["max_energy_err_vs_fp64_gpu_eV_per_atom"] = float(de32.max())
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import core
+        opot = core.EAMPotential.from_table(tab)
+        t0 = time.perf_counter()
+        e_or = np.array([core.eam(r.pos, r.box, opot).energy for r in reps])
+        dt = time.perf_counter() - t0
+        cpu = {"value": len(reps) / dt, "unit": "replica-evals/s", "cores": core.num_threads(),
+               "kind": "oracle",
+               "sample": "one FP64 O(N^2) evaluation of all 64 replicas (%d atoms), %.1f s"
+                         % (n_tot, dt)}
+        for name in ("fp32", "fp64"):
+            res[name]["max_energy_err_vs_oracle_eV_per_atom"] = float(
+                np.max(np.abs(e_gpu[name][0] - e_or) / per_atom))
+    head = res["fp32"]
+    out = {
+        "metric": "replica-evals/s (64 batched Cu cold-curve replicas: energy, forces, virial)",
+        "value": head["replica_evals_per_s"], "unit": "replica-evals/s", "n_gpus": 1,
+        "steps": evals, "warmup": 2, "ms_per_step": head["ms_per_eval_batched"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "64 perfect Cu fcc replicas, n^3 cells with n drawn from "
+                               "4..12, a = linspace(3.30, 4.20, 64), EAM Cu 2000-point splines",
+                   "n_atoms": n_tot},
+        "paths": res,
+        "speedup_fp32_over_fp64": res["fp64"]["ms_per_eval_batched"] / head["ms_per_eval_batched"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_force_matching(args):
+    """Force matching on 1024 Cu snapshots of 500 atoms: forward (forces of the trainable
+    splines), loss and hand-written adjoint per epoch; adjoint vs FP64 central differences."""
+    import torch
+    import mdinputs as mi
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd import fm, md
+    N.lib()
+    tab = mi.force_matching_tables()
+    noise = torch.as_tensor(mi.coefficient_noise(), device="cuda")
+    snaps = mi.force_matching_snapshots()
+    n_atoms = sum(len(s.pos) for s in snaps)
+    fits = [md.md_spline_fit(tf.y, tf.h, tf.dy_lo, tf.dy_hi) for tf in (tab.phi, tab.rho, tab.emb)]
+    res = {}
+    for name, prec in (("fp64", N.MD_FP64), ("fp32", N.MD_FP32)):
+        pot = md.EAMPotential(fits[0] * noise[:64], fits[1] * noise[64:128], fits[2] * noise[128:],
+                              tab.rho.x_lo, tab.rho.h, tab.emb.x_lo, tab.emb.h, mi.EAM_CU.r_cut)
+        batch = fm.SnapshotBatch(snaps, mi.EAM_CU.r_cut + 0.3, precision=prec)
+        ref_pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
+        f_ref = batch.forces(ref_pot, saved=False).clone()
+        coef = torch.cat([c.clone() for c in pot.coef]).requires_grad_(True)
+
+        def epoch():
+            coef.grad = None
+            loss = fm.force_matching_loss(coef, batch, pot, f_ref)
+            loss.backward()
+            return loss
+
+        for _ in range(3):
+            epoch()
+        reps = max(10, (args.steps or 1000) // 50)
+        ms = _gpu_time(epoch, reps) / reps
+        loss = epoch().item()
+        g = coef.grad.detach().cpu().numpy()
+        batch.state.check_flags()
+        r = {"ms_per_epoch": ms, "epochs_per_s": 1e3 / ms, "atoms_per_s": n_atoms / (ms * 1e-3),
+             "loss": loss}
+        if prec == N.MD_FP64:
+            h = 1e-6
+            errs = []
+            for k in (5, 20, 40, 64 + 10, 64 + 40, 128 + 20, 128 + 33, 128 + 50):
+                cp = coef.detach().clone()
+                cm = coef.detach().clone()
+                cp[k] += h
+                cm[k] -= h
+                lp = fm.force_matching_loss(cp, batch, pot, f_ref).item()
+                lm = fm.force_matching_loss(cm, batch, pot, f_ref).item()
+                errs.append(abs((lp - lm) / (2 * h) - g[k]))
+            r["adjoint_vs_fd_max_abs_err"] = float(max(errs))
+            r["adjoint_vs_fd_rel_to_max_grad"] = float(max(errs) / np.max(np.abs(g)))
+            res["grad_fp64"] = g
+        else:
+            r["grad_rel_err_vs_fp64_gpu"] = float(np.max(np.abs(g - res["grad_fp64"]))
+                                                  / np.max(np.abs(res["grad_fp64"])))
+        res[name] = r
+    res.pop("grad_fp64")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import adjoint as oadj
+        from oracle import core
+        from oracle import spline as osp
+        sample = 16
+        grids = tuple(oadj.Grid(tf.x_lo, tf.h, tf.K + 2) for tf in (tab.phi, tab.rho, tab.emb))
+        nz = noise.cpu().numpy()
+        c_or = [osp.fit_table(tf) * nz[64 * b:64 * (b + 1)]
+                for b, tf in enumerate((tab.phi, tab.rho, tab.emb))]
+        osn = [oadj.Snapshot(s.pos, s.box, mi.EAM_CU.r_cut) for s in snaps[:sample]]
+        apot = core.EAMPotential.analytic(mi.EAM_CU)
+        t0 = time.perf_counter()
+        f_ref_or = [core.eam(s.pos, s.box, apot).force for s in snaps[:sample]]
+        oadj.gradient(osn, c_or, grids, f_ref_or)
+        dt = time.perf_counter() - t0
+        cpu = {"value": sample / len(snaps) / dt, "unit": "epochs/s", "cores": core.num_threads(),
+               "kind": "oracle",
+               "sample": "reference forces, loss and chain-rule gradient of %d of the %d "
+                         "snapshots, %.1f s, scaled to one epoch" % (sample, len(snaps), dt)}
+    out = {
+        "metric": "force-matching epochs/s (1024 Cu snapshots x 500 atoms, forward + adjoint)",
+        "value": res["fp64"]["epochs_per_s"], "unit": "epochs/s", "n_gpus": 1,
+        "steps": max(10, (args.steps or 1000) // 50), "warmup": 3, "ms_per_step": res["fp64"]["ms_per_epoch"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "1024 Cu fcc 5^3 snapshots, a ~ U(3.55, 3.68), N(0, 0.1^2) "
+                               "displacements; 3 x 64 B-spline coefficients with 5% noise",
+                   "n_atoms": n_atoms},
+        "paths": res, "cpu_baseline": cpu,
+    }
     print(json.dumps(out), flush=True)
 
 

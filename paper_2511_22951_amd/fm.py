@@ -8,6 +8,8 @@ Torch only evaluates the loss and holds memory.
 """
 from __future__ import annotations
 
+import ctypes as C
+
 import numpy as np
 import torch
 
@@ -48,7 +50,10 @@ class SnapshotBatch:
 
     def backward(self, pot: md.EAMPotential, grad_force):
         g = grad_force.to(torch.float64).contiguous()
-        return md.md_eam_backward(self.state, pot, self.nl, self.saved, g)
+        nb = int(N.lib().md_backward_workspace_bytes(C.byref(self.plan.c), C.byref(pot.c)))
+        if self.bws is None or self.bws.numel() < nb:
+            self.bws = torch.zeros(max(nb, 1), dtype=torch.uint8, device=self.state.pos.device)
+        return md.md_eam_backward(self.state, pot, self.nl, self.saved, g, ws=self.bws)
 
 
 class EAMForces(torch.autograd.Function):

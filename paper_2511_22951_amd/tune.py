@@ -87,3 +87,20 @@ def best_lanes(system, prec, candidates=CANDIDATES, samples=10, use_cache=True):
     if use_cache:
         _store(cache)
     return int(best)
+
+
+def pick(key_parts, candidates, time_fn, use_cache=True):
+    """Generic tuner: time_fn(candidate) -> duration (any unit); returns the fastest
+    candidate, cached per (device, key_parts)."""
+    import torch
+
+    key = "|".join([torch.cuda.get_device_name(0)] + [str(k) for k in key_parts])
+    cache = _load() if use_cache else {}
+    if key in cache and cache[key].get("choice") in candidates:
+        return cache[key]["choice"]
+    results = {c: float(time_fn(c)) for c in candidates}
+    best = min(results, key=results.get)
+    cache[key] = {"choice": best, "times": {str(k): v for k, v in results.items()}}
+    if use_cache:
+        _store(cache)
+    return best
