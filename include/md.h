@@ -230,8 +230,10 @@ int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos, double* v
  * r_ns = r_c + skin) by scanning the 3x3x3 block of cells around each atom's
  * cell (de-duplicated when a box has fewer than 3 cells on an axis).  Distances
  * use the minimum image in FP64 with no fused multiply-add, so the set equals
- * the brute-force definition bit for bit.  Sets MD_FLAG_NEIGH_OVERFLOW when an
- * atom has more than max_neigh neighbours. */
+ * the brute-force definition bit for bit.  Each list is in candidate order
+ * (stencil cell, then position in the cell), so lists are reproducible run to
+ * run.  Sets MD_FLAG_NEIGH_OVERFLOW when an atom has more than max_neigh
+ * neighbours (the first max_neigh are kept). */
 int md_build_neighbors(const md_batch* b, md_rebuild_mode mode, const double* pos,
                        const int* cell_start, const md_nlist* nl, void* ctl, void* stream);
 

@@ -173,75 +173,61 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_bin_copyback(
 }
 
 // ---------------------------------------------------------------------------
-// Verlet list: scan the (de-duplicated) 3x3x3 block of cells around each atom.
+// Verlet list (Sec. 1.4): the candidates of every atom of a cell are the atoms of
+// the (de-duplicated) 3x3x3 block of cells around it, the same set for all atoms
+// of the cell.  One wavefront takes one cell: its lanes hold 64 candidates at a
+// time (positions in registers, loaded once per cell rather than once per atom)
+// and test them against each atom of the cell in turn; a ballot of the accepted
+// lanes gives every accepted candidate its slot, so the list is written in
+// candidate order (stencil cell order, then cell order) in a single pass.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int stencil_axis(int c, int nc, int periodic, int* out) {
-  int m = 0;
-  if (periodic) {
-    if (nc >= 3) {
-      out[m++] = c == 0 ? nc - 1 : c - 1;
-      out[m++] = c;
-      out[m++] = c == nc - 1 ? 0 : c + 1;
-    } else if (nc == 2) {
-      out[m++] = 0;
-      out[m++] = 1;
-    } else {
-      out[m++] = 0;
-    }
-  } else {
-    if (c > 0) out[m++] = c - 1;
-    out[m++] = c;
-    if (c < nc - 1) out[m++] = c + 1;
+constexpr int CW = 4;                  // wavefronts (cells) per block
+constexpr int CELL_BLOCK = CW * MD_WAVE;
+
+// Stencil cell t (0..2) along one axis for an atom in cell c: the cell index, or -1
+// when there is none (outside a non-periodic box, or a duplicate when nc < 3), and
+// the image k = rint(d / L) that a candidate in it has (d = x_j - x_i): +1 for a
+// cell reached by wrapping below 0, -1 by wrapping above nc - 1.
+__device__ __forceinline__ int stencil_cell(int c, int t, int nc, int periodic, int& k) {
+  k = 0;
+  if (periodic && nc < 3) return t < nc ? t : -1;
+  int q = c + t - 1;
+  if (q < 0) {
+    if (!periodic) return -1;
+    q += nc;
+    k = 1;
+  } else if (q >= nc) {
+    if (!periodic) return -1;
+    q -= nc;
+    k = -1;
   }
-  return m;
+  return q;
 }
 
-// Verlet list with BL lanes per atom.  The atom's candidates are the atoms of the
-// (de-duplicated) 3x3x3 cell block, taken as up to 27 index ranges (three
-// z-neighbouring cells that do not wrap form one range).  The atom's BL lanes
-// walk each range in lock step, BL consecutive candidates per round; a wavefront
-// ballot of the accepted flags gives every accepted candidate its slot (the
-// number of accepted candidates before it), so one pass writes the list in
-// candidate order: deterministic, and neighbouring atoms get similar lists.
-// The tile's 64 lists are assembled in LDS and written out row by row, each
-// row of the strided layout being one contiguous segment (coalesced stores).
-constexpr int BL = 8;
-constexpr int BU = 4;                  // candidate rounds per trip (loads in flight)
-constexpr int BUILD_BLOCK = 64 * BL;  // one work tile per block
-constexpr int MAX_STAGED = 192;       // 64 lists of this length + ranges fit 64 KB of LDS
+// Test modes: PLAIN for a cell whose block does not wrap (d itself is the minimum
+// image: |d| < 2 w <= 2 L / 5 < L / 2 when nc >= 5), SHIFT for a wrapping block
+// with nc >= 5 on every periodic axis (the image of each stencil cell is fixed, so
+// d - L k is the minimum image, the same operations as d - L rint(d / L)), RINT
+// for small grids (nc < 5 on a periodic axis): the minimum image per candidate.
+enum { PLAIN = 0, SHIFT = 1, RINT = 2 };
 
+struct Cand {
+  double x, y, z;     // candidate position
+  double sx, sy, sz;  // L k per axis (SHIFT)
+  int j;              // candidate index
+  bool valid;
+};
 
-// r^2 < r_ns^2 for the pair, with the minimum image when IMG.  Without it the
-// result is identical: for an atom whose cell block does not wrap, |d| < L/2 and
-// d - L rint(d / L) = d - 0 = d exactly.
-template <bool IMG>
-__device__ __forceinline__ bool accept(const double4& p, const double4& q, const double* len,
-                                       const double* inv, const int* per, double rns2) {
-  double dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-  if (IMG) {
-    if (per[0]) dx = dx - len[0] * rint(dx * inv[0]);
-    if (per[1]) dy = dy - len[1] * rint(dy * inv[1]);
-    if (per[2]) dz = dz - len[2] * rint(dz * inv[2]);
-  }
-  const double r2 = (dx * dx + dy * dy) + dz * dz;
-  return r2 < rns2;
-}
-
-template <bool STAGE>
-__global__ __launch_bounds__(BUILD_BLOCK) void k_build(md_batch b, int mode,
-                                                       const double4* __restrict__ pos,
-                                                       const int* __restrict__ cell_start,
-                                                       int* neigh, int* nneigh, int max_neigh,
-                                                       int lanes_log2, int npad, double rns2,
-                                                       md_ctl_dev* ctl) {
-  if (skip_rebuild(mode, ctl)) return;
-  const int t = md_remap_block(b.n_tiles);
-  if (t >= b.n_tiles) return;
-  const md_tile T = b.tiles[t];
-  const md_domain& D = b.domains[T.rep];
-  const int a = threadIdx.x / BL, l = threadIdx.x % BL;
-  const bool active = a < T.count;
-  const int i = T.first + (active ? a : 0);
+template <int MODE>
+__device__ __forceinline__ void cell_lists(const md_domain& D, int a0, int na, int C,
+                                           const int* s_beg, const int* s_start,
+                                           const int* s_code, double (*s_p)[MD_WAVE],
+                                           const double4* __restrict__ pos, int* neigh,
+                                           int* nneigh, int max_neigh, int lanes_log2, int npad,
+                                           double rns2, bool img, md_ctl_dev* ctl) {
+  const int lane = threadIdx.x & (MD_WAVE - 1);
+  const int lanes = 1 << lanes_log2;
+  const size_t row = (size_t)npad * lanes;
   double len[3], inv[3];
   int per[3];
 #pragma unroll
@@ -250,106 +236,151 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build(md_batch b, int mode,
     inv[q] = D.inv_len[q];
     per[q] = D.periodic[q];
   }
-  const double4 p = pos[i];
-  const int cx = cell_coord(p.x, D.lo[0], D.inv_w[0], D.nc[0]);
-  const int cy = cell_coord(p.y, D.lo[1], D.inv_w[1], D.nc[1]);
-  const int cz = cell_coord(p.z, D.lo[2], D.inv_w[2], D.nc[2]);
-  int sx[3], sy[3], sz[3];
-  const int mx = stencil_axis(cx, D.nc[0], D.periodic[0], sx);
-  const int my = stencil_axis(cy, D.nc[1], D.periodic[1], sy);
-  const int mz = stencil_axis(cz, D.nc[2], D.periodic[2], sz);
-  const bool zrun = (mz == 3) && (sz[0] + 1 == sz[1]) && (sz[1] + 1 == sz[2]);
-  // the atom's candidate ranges, shared by its lanes through LDS; the (x, y)
-  // columns of the stencil are spread over the atom's lanes so that their
-  // cell_start lookups are in flight together
-  __shared__ int2 s_rng[64][27];
-  __shared__ int s_nr[64];
-  {
-    const int ncol = mx * my, per_col = zrun ? 1 : mz;
-    for (int c = l; c < ncol; c += BL) {
-      const int ix = c / my, iy = c - ix * my;
-      const int col = D.cell_off + (sx[ix] * D.nc[1] + sy[iy]) * D.nc[2];
-      if (zrun) {
-        s_rng[a][c] = make_int2(cell_start[col + sz[0]], cell_start[col + sz[2] + 1]);
-      } else {
-        for (int iz = 0; iz < mz; ++iz)
-          s_rng[a][c * mz + iz] = make_int2(cell_start[col + sz[iz]], cell_start[col + sz[iz] + 1]);
-      }
+  // candidate v of the flattened stencil: range r = the last with s_beg[r] <= v
+  auto make = [&](int v) {
+    Cand c;
+    c.valid = v < C;
+    int r = 0;
+#pragma unroll
+    for (int st = 16; st > 0; st >>= 1)
+      if (s_beg[r + st] <= v) r += st;
+    c.j = c.valid ? s_start[r] + (v - s_beg[r]) : a0;
+    const double4 q = pos[c.j];
+    c.x = q.x;
+    c.y = q.y;
+    c.z = q.z;
+    const int code = s_code[r];
+    const int kx = (code & 3) - 1, ky = ((code >> 2) & 3) - 1, kz = ((code >> 4) & 3) - 1;
+    c.sx = kx == 0 ? 0.0 : (kx > 0 ? len[0] : -len[0]);
+    c.sy = ky == 0 ? 0.0 : (ky > 0 ? len[1] : -len[1]);
+    c.sz = kz == 0 ? 0.0 : (kz > 0 ? len[2] : -len[2]);
+    return c;
+  };
+  int over = 0, most = 0;
+  for (int g0 = 0; g0 < na; g0 += MD_WAVE) {
+    const int gc = min(MD_WAVE, na - g0);
+    if (lane < gc) {
+      const double4 q = pos[a0 + g0 + lane];
+      s_p[0][lane] = q.x;
+      s_p[1][lane] = q.y;
+      s_p[2][lane] = q.z;
     }
-    if (l == 0) s_nr[a] = active ? ncol * per_col : 0;
-  }
-  __syncthreads();
-  const int nrng = s_nr[a];
-  extern __shared__ int s_list[];  // [64][max_neigh]
-  bool img = false;
-  if (D.periodic[0]) img |= (D.nc[0] < 3) || cx == 0 || cx == D.nc[0] - 1;
-  if (D.periodic[1]) img |= (D.nc[1] < 3) || cy == 0 || cy == D.nc[1] - 1;
-  if (D.periodic[2]) img |= (D.nc[2] < 3) || cz == 0 || cz == D.nc[2] - 1;
-  // the minimum-image test is taken by the whole wavefront when any of its atoms
-  // needs it (for the others it gives the identical result)
-  const bool wimg = __any(img);
-  const int lanes = 1 << lanes_log2;
-  const int gshift = (threadIdx.x & (MD_WAVE - 1)) & ~(BL - 1);  // the atom's lanes in the ballot
-  const unsigned below = (1u << l) - 1u;
-  int total = 0;
-  for (int r = 0; r < nrng; ++r) {
-    const int jb = s_rng[a][r].x, je = s_rng[a][r].y;
-    // BU rounds of BL candidates per trip, their loads issued together
-    for (int j0 = jb; j0 < je; j0 += BL * BU) {
-      double4 q[BU];
-#pragma unroll
-      for (int u = 0; u < BU; ++u) q[u] = pos[min(j0 + u * BL + l, je - 1)];
-#pragma unroll
-      for (int u = 0; u < BU; ++u) {
-        const int j = j0 + u * BL + l;
-        const bool in = wimg ? accept<true>(p, q[u], len, inv, per, rns2)
-                             : accept<false>(p, q[u], len, inv, per, rns2);
-        const bool ok = (j < je) & (j != i) & in;
-        const unsigned g = (unsigned)(__ballot(ok) >> gshift) & ((1u << BL) - 1u);
-        if (ok) {
-          const int slot = total + __popc(g & below);
-          if (slot < max_neigh) {
-            if (STAGE)
-              s_list[a * max_neigh + slot] = j;
-            else
-              neigh[((size_t)(slot >> lanes_log2) * npad + i) * lanes + (slot & (lanes - 1))] = j;
-          }
+    __builtin_amdgcn_wave_barrier();
+    int tot = 0;  // lane k: accepted candidates of atom g0 + k so far
+    Cand nx = make(lane);
+    for (int v0 = 0; v0 < C; v0 += MD_WAVE) {
+      const Cand c = nx;
+      if (v0 + MD_WAVE < C) nx = make(v0 + MD_WAVE + lane);  // next chunk in flight
+      for (int k = 0; k < gc; ++k) {
+        const int ia = a0 + g0 + k;
+        double dx = c.x - s_p[0][k], dy = c.y - s_p[1][k], dz = c.z - s_p[2][k];
+        if (MODE == SHIFT) {
+          dx = dx - c.sx;
+          dy = dy - c.sy;
+          dz = dz - c.sz;
+        } else if (MODE == RINT) {
+          if (per[0]) dx = dx - len[0] * rint(dx * inv[0]);
+          if (per[1]) dy = dy - len[1] * rint(dy * inv[1]);
+          if (per[2]) dz = dz - len[2] * rint(dz * inv[2]);
         }
-        total += __popc(g);
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        const bool ok = c.valid & (c.j != ia) & (r2 < rns2);
+        const unsigned long long m = __ballot(ok);
+        const int slot = __builtin_amdgcn_readlane(tot, k) +
+                         (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (ok && slot < max_neigh)
+          neigh[(size_t)(slot >> lanes_log2) * row + (size_t)ia * lanes + (slot & (lanes - 1))] =
+              c.j;
+        tot += lane == k ? (int)__popcll(m) : 0;
       }
     }
-  }
-  if (STAGE) {
-    // coalesced write-out: row q of the layout holds entries q*lanes .. q*lanes+lanes-1
-    // of every atom; the tile's atoms occupy 64*lanes consecutive ints of each row.
-    __shared__ int s_cnt[64];
-    if (l == 0) s_cnt[a] = active ? min(total, max_neigh) : 0;
-    __syncthreads();
-    int tmax = 0;
-    for (int q = 0; q < 64; ++q) tmax = max(tmax, s_cnt[q]);
-    const int rows = (tmax + lanes - 1) >> lanes_log2;
-    const int span = 64 * lanes;
-    for (int e = threadIdx.x; e < rows * span; e += blockDim.x) {
-      const int q = e / span, w = e - q * span;
-      const int aa = w >> lanes_log2, m = q * lanes + (w & (lanes - 1));
-      if (aa < T.count && m < s_cnt[aa])
-        neigh[((size_t)q * npad + T.first) * lanes + w] = s_list[aa * max_neigh + m];
+    if (lane < gc) {
+      nneigh[a0 + g0 + lane] = (tot < max_neigh ? tot : max_neigh) | (img ? MD_NN_IMG : 0);
+      over |= tot > max_neigh;
+      most = max(most, tot);
     }
-  }
-  int over = 0, wmax = 0;
-  if (active && l == 0) {
-    // img: the stencil crosses a periodic boundary (wrapped cell, or fewer than 3 cells)
-    nneigh[i] = (total < max_neigh ? total : max_neigh) | (img ? MD_NN_IMG : 0);
-    over = total > max_neigh;
-    wmax = total;
+    __builtin_amdgcn_wave_barrier();
   }
   if (__any(over)) {
-    if ((threadIdx.x & (MD_WAVE - 1)) == 0) md_flag(ctl, MD_FLAG_NEIGH_OVERFLOW);
+    if (lane == 0) md_flag(ctl, MD_FLAG_NEIGH_OVERFLOW);
   }
-  // One atomic per wavefront for the running maximum of the list length.
 #pragma unroll
-  for (int o = MD_WAVE / 2; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, MD_WAVE));
-  if ((threadIdx.x & (MD_WAVE - 1)) == 0 && wmax > 0) atomicMax(&ctl->max_nneigh, wmax);
+  for (int o = MD_WAVE / 2; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o, MD_WAVE));
+  if (lane == 0 && most > 0) atomicMax(&ctl->max_nneigh, most);
+}
+
+__global__ __launch_bounds__(CELL_BLOCK) void k_build(md_batch b, int mode,
+                                                      const double4* __restrict__ pos,
+                                                      const int* __restrict__ cell_start,
+                                                      int* neigh, int* nneigh, int max_neigh,
+                                                      int lanes_log2, int npad, double rns2,
+                                                      md_ctl_dev* ctl) {
+  if (skip_rebuild(mode, ctl)) return;
+  __shared__ int s_beg[CW][33], s_start[CW][32], s_code[CW][32];
+  __shared__ double s_p[CW][3][MD_WAVE];
+  const int w = threadIdx.x / MD_WAVE, lane = threadIdx.x & (MD_WAVE - 1);
+  const int cell = md_remap_block((b.n_cells + CW - 1) / CW) * CW + w;
+  if (cell >= b.n_cells) return;  // whole wavefronts only
+  // the box of this cell: the last domain whose cells start at or before it
+  int lo = 0, hi = b.n_rep - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.domains[mid].cell_off <= cell) lo = mid; else hi = mid - 1;
+  }
+  const md_domain& D = b.domains[lo];
+  const int a0 = cell_start[cell], na = cell_start[cell + 1] - a0;
+  if (na == 0) return;
+  const int local = cell - D.cell_off;
+  const int c2 = local % D.nc[2], c1 = (local / D.nc[2]) % D.nc[1], c0 = local / (D.nc[2] * D.nc[1]);
+  // lane t < 27 takes stencil cell (t / 9, t / 3 % 3, t % 3): its atom range and image
+  int cnt = 0, start = 0, code = 0;
+  if (lane < 27) {
+    int kx, ky, kz;
+    const int qx = stencil_cell(c0, lane / 9, D.nc[0], D.periodic[0], kx);
+    const int qy = stencil_cell(c1, (lane / 3) % 3, D.nc[1], D.periodic[1], ky);
+    const int qz = stencil_cell(c2, lane % 3, D.nc[2], D.periodic[2], kz);
+    if (qx >= 0 && qy >= 0 && qz >= 0) {
+      const int q = D.cell_off + (qx * D.nc[1] + qy) * D.nc[2] + qz;
+      start = cell_start[q];
+      cnt = cell_start[q + 1] - start;
+      code = (kx + 1) | ((ky + 1) << 2) | ((kz + 1) << 4);
+    }
+  }
+  // exclusive prefix of the range sizes over the lanes
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 32; o <<= 1) {
+    const int u = __shfl_up(incl, o, MD_WAVE);
+    if (lane >= o) incl += u;
+  }
+  const int C = __shfl(incl, 31, MD_WAVE);
+  if (lane < 32) {
+    s_beg[w][lane] = lane < 27 ? incl - cnt : C;
+    s_start[w][lane] = start;
+    s_code[w][lane] = code;
+  }
+  if (lane == 0) s_beg[w][32] = C;
+  __builtin_amdgcn_wave_barrier();
+  // the block wraps (image flag for the force passes), and the test mode
+  bool img = false, small = false;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int cq = q == 0 ? c0 : (q == 1 ? c1 : c2);
+    if (D.periodic[q]) {
+      img |= (D.nc[q] < 3) || cq == 0 || cq == D.nc[q] - 1;
+      small |= D.nc[q] < 5;
+    }
+  }
+  if (small)
+    cell_lists<RINT>(D, a0, na, C, s_beg[w], s_start[w], s_code[w], s_p[w], pos, neigh, nneigh,
+                     max_neigh, lanes_log2, npad, rns2, img, ctl);
+  else if (img)
+    cell_lists<SHIFT>(D, a0, na, C, s_beg[w], s_start[w], s_code[w], s_p[w], pos, neigh, nneigh,
+                      max_neigh, lanes_log2, npad, rns2, img, ctl);
+  else
+    cell_lists<PLAIN>(D, a0, na, C, s_beg[w], s_start[w], s_code[w], s_p[w], pos, neigh, nneigh,
+                      max_neigh, lanes_log2, npad, rns2, img, ctl);
 }
 
 }  // namespace
@@ -407,20 +438,10 @@ extern "C" int md_build_neighbors(const md_batch* b, md_rebuild_mode mode, const
   if (lg < 0 || nl->max_neigh < nl->lanes || nl->max_neigh % nl->lanes) return MD_ERR_ARG;
   if (!(b->r_ns > 0.0)) return MD_ERR_ARG;
   if (b->n_atoms == 0) return MD_OK;
-  const dim3 grid(md_grid_blocks(b->n_tiles)), block(BUILD_BLOCK);
-  // Lists are staged in LDS (coalesced write-out) when the tile's 64 lists fit
-  // beside the static ranges within 64 KB; longer lists are stored directly.
-  const size_t lds = (size_t)64 * nl->max_neigh * sizeof(int);
-  if (nl->max_neigh <= MAX_STAGED)
-    MD_LAUNCH_TIMED(MD_KERNEL_BUILD, k_build<true>, grid, block, lds, (hipStream_t)stream, *b,
-                    (int)mode, (const double4*)pos, cell_start, nl->neigh, nl->nneigh,
-                    nl->max_neigh, lg, md_npad(b->n_atoms), b->r_ns * b->r_ns,
-                    (md_ctl_dev*)ctl);
-  else
-    MD_LAUNCH_TIMED(MD_KERNEL_BUILD, k_build<false>, grid, block, 0, (hipStream_t)stream, *b,
-                    (int)mode, (const double4*)pos, cell_start, nl->neigh, nl->nneigh,
-                    nl->max_neigh, lg, md_npad(b->n_atoms), b->r_ns * b->r_ns,
-                    (md_ctl_dev*)ctl);
+  const dim3 grid(md_grid_blocks((b->n_cells + CW - 1) / CW)), block(CELL_BLOCK);
+  MD_LAUNCH_TIMED(MD_KERNEL_BUILD, k_build, grid, block, 0, (hipStream_t)stream, *b, (int)mode,
+                  (const double4*)pos, cell_start, nl->neigh, nl->nneigh, nl->max_neigh, lg,
+                  md_npad(b->n_atoms), b->r_ns * b->r_ns, (md_ctl_dev*)ctl);
   MD_LAUNCH_CHECK();
   return MD_OK;
 }
