@@ -161,13 +161,14 @@ def run_path(system, prec, lanes, args):
         else:
             kt[kname] = time_kernel(N, kname, lambda: sim.step(), args.kernel_samples)
     nneigh = sim.nl.lengths().double().mean().item()
+    rebuild_ms = _gpu_time(lambda: sim.rebuild(), 5) / 5  # binning + list, after the run
     torch.cuda.synchronize()
     return {
         "ms": ms, "steps": args.steps, "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"],
         "drift_ev_per_atom_ps": slope, "e0_per_atom": float(etot[0]),
         "energy_span_per_atom": float(np.max(etot) - np.min(etot)),
         "kernels_ms": kt, "mean_neigh": nneigh, "max_nneigh": info["max_nneigh"], "f0": f0,
-        "lanes": lanes, "rebuild_every": k,
+        "lanes": lanes, "rebuild_every": k, "rebuild_ms": rebuild_ms,
     }
 
 
@@ -294,6 +295,7 @@ def main():
                     "nve_drift_eV_per_atom_ps": r["drift_ev_per_atom_ps"],
                     "energy_span_eV_per_atom": r["energy_span_per_atom"],
                     "kernel_us": {kk: 1e3 * v[0] for kk, v in r["kernels_ms"].items()},
+                    "rebuild_us": 1e3 * r["rebuild_ms"],
                     "force_rel_err_vs_oracle": ferr.get(k)}
     if "fp32" in results and "fp64" in results:
         paths["fp32"]["force_rel_err_vs_fp64_gpu"] = float(
@@ -365,6 +367,7 @@ def bench_al_shock(args):
         kt[kname] = time_kernel(N, kname, lambda: sim.step(), args.kernel_samples)[0]
     nn = sim.nl.lengths().double()
     zc = sim.state.positions()[:, 2]
+    rebuild_ms = _gpu_time(lambda: sim.rebuild(), 5) / 5
     kt_force = kt["eam_force"] * 1e-3
     bytes_force = algorithmic_force_bytes(n, nn.mean().item(), 4)
     achieved = bytes_force / kt_force / 1e9
@@ -386,6 +389,7 @@ def bench_al_shock(args):
         "piston_z_end": float(system.walls["piston_v"] * info["step"] * system.dt_ps),
         "atoms_min_z": float(zc.min()),
         "kernel_us": {k: 1e3 * v for k, v in kt.items()},
+        "rebuild_us": 1e3 * rebuild_ms,
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

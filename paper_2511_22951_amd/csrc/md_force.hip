@@ -29,7 +29,8 @@ template <> __device__ __forceinline__ float rsqrt_r<float>(float x) { return __
 
 struct TabGeom {
   double r_lo, r_inv_h, e_lo, e_inv_h;
-  int nr, ne;  // intervals
+  int nr, ne;      // intervals (FP64 r grid, embedding)
+  double q_lo, q_inv_h;  // FP32 pair tables: r^2 grid of MD_STAB_N intervals
 };
 
 // Interval index and local coordinate; sets oor when x is below the table.
@@ -80,14 +81,36 @@ struct Img {
 // periodic boundary; for the others the plain difference is the minimum image,
 // since positions are wrapped at every rebuild and drift less than half a skin).
 template <bool IMG>
-__device__ __forceinline__ Sep separation(const Img& D, double4 pj, double4 pi) {
+__device__ __forceinline__ Sep separation(const Img& D, double4 pj, double4 pi, Sep& shift) {
   Sep d{pj.x - pi.x, pj.y - pi.y, pj.z - pi.z};
   if (IMG) {
-    d.x -= D.len[0] * rint(d.x * D.inv[0]);
-    d.y -= D.len[1] * rint(d.y * D.inv[1]);
-    d.z -= D.len[2] * rint(d.z * D.inv[2]);
+    shift.x = D.len[0] * rint(d.x * D.inv[0]);
+    shift.y = D.len[1] * rint(d.y * D.inv[1]);
+    shift.z = D.len[2] * rint(d.z * D.inv[2]);
+    d.x -= shift.x;
+    d.y -= shift.y;
+    d.z -= shift.z;
   }
   return d;
+}
+
+// Rows of the pair tables: the r grid's intervals (FP64), the r^2 grid's (FP32).
+template <typename R>
+__device__ __host__ __forceinline__ int pair_rows(const TabGeom& g) {
+  return sizeof(R) == 4 ? MD_STAB_N : g.nr;
+}
+
+// FP32 pair-table row and local coordinate for squared distance q (r^2 grid; the
+// index is clamped, pairs outside the table are masked or flagged by the caller).
+__device__ __forceinline__ int qtab_index(float q, float inv_h, float lo_inv_h, float& t) {
+  const float u = q * inv_h - lo_inv_h;
+  const int k = min(max((int)u, 0), MD_STAB_N - 1);
+  t = u - (float)k;
+  return k;
+}
+
+__device__ __forceinline__ float cubic(const float* a, float t) {
+  return ((a[3] * t + a[2]) * t + a[1]) * t + a[0];
 }
 
 // Blocks of the force passes: 1024 threads = TPB work tiles of 64 atoms x LANES lanes.
@@ -165,6 +188,30 @@ __device__ __forceinline__ void visit_list(const int* neigh, uint32_t e0, uint32
     for (int u = 0; u < U; ++u) pair(q[u]);
   }
   for (; m < nn; m += LANES, e += stride) pair(load(load_idx(neigh, e)));
+}
+
+// Software-pipelined variant for the EAM passes: the list indices of the next U
+// entries are loaded while the records of the current U are in flight, so a lane
+// waits for one round trip per U entries instead of two.  A lane's last block is
+// padded with its own atom (`self`); pair(q, valid) masks those entries.
+template <int LANES, int U, typename Load, typename Pair>
+__device__ __forceinline__ void visit_list_pipe(const int* neigh, uint32_t e0, uint32_t stride,
+                                                int l, int nn, int self, Load load, Pair pair) {
+  const int cnt = nn > l ? (nn - l + LANES - 1) / LANES : 0;  // this lane's entries
+  int jn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) jn[u] = u < cnt ? load_idx(neigh, e0 + u * stride) : self;
+  uint32_t e = e0 + U * stride;
+  for (int b0 = 0; b0 < cnt; b0 += U) {
+    decltype(load(0)) q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = load(jn[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) jn[u] = b0 + U + u < cnt ? load_idx(neigh, e + u * stride) : self;
+    e += U * stride;
+#pragma unroll
+    for (int u = 0; u < U; ++u) pair(q[u], b0 + u < cnt);
+  }
 }
 
 // F'(rhobar) travels to the force pass in the w slot of the position record: as a
@@ -267,14 +314,15 @@ __device__ __forceinline__ void step_bookkeeping(md_ctl_dev* ctl) {
 // EAM pass 1: rhobar_i = sum_j rho(r_ij), F'(rhobar_i) into pos[i].w, energy.
 // ---------------------------------------------------------------------------
 template <typename R, int LANES, bool EV, bool TLDS>
-__global__ __launch_bounds__(FBLOCK) void k_eam_density(
-    md_batch b, double4* pos, const int* __restrict__ neigh, const int* __restrict__ nneigh,
-    int npad, const R* __restrict__ rtab_g, const R* __restrict__ etab, TabGeom g, R rc2,
-    double* saved, double* partial, long long* ev, int ev_cap, md_ctl_dev* ctl) {
+__device__ __forceinline__ void eam_density_body(
+    const md_batch& b, double4* pos, const int* __restrict__ neigh,
+    const int* __restrict__ nneigh, int npad, const R* __restrict__ rtab_g,
+    const R* __restrict__ etab, const TabGeom& g, R rc2, double* saved, double* partial,
+    long long* ev, int ev_cap, md_ctl_dev* ctl) {
   constexpr int U = 4;  // neighbours in flight per lane
   extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
-  const R* rtab = TLDS ? stage_table<R, MD_RTAB_W>(rtab_g, g.nr, (R*)s_dyn) : rtab_g;
+  const R* rtab = TLDS ? stage_table<R, MD_RTAB_W>(rtab_g, pair_rows<R>(g), (R*)s_dyn) : rtab_g;
   if (EV && blockIdx.x == 0) zero_record(b, ev, ev_cap, ctl->step_next);
   step_bookkeeping(ctl);
   const Slot S = force_slot<LANES>(b.n_tiles);
@@ -292,35 +340,48 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_density(
   }
   const bool wimg = __any(raw & MD_NN_IMG);
   R rho = 0, phi = 0;
+  float min_r2 = 3.0e38f;  // FP32: smallest r^2 seen (range check against the table)
   if (i >= 0) {
     const Img D(&b.domains[T.rep]);
     const double4 pi = load_xyz(pos, i);
     const R rih = (R)g.r_inv_h, rloh = (R)(g.r_lo * g.r_inv_h);
+    const float qih = (float)g.q_inv_h, qloh = (float)(g.q_lo * g.q_inv_h);
     const uint32_t e0 = (uint32_t)i * LANES + S.l, stride = (uint32_t)npad * LANES;
     auto run = [&](auto img_tag) {
       constexpr bool IMG = decltype(img_tag)::value;
-      auto pair = [&](double4 pj) {
-        const Sep d = separation<IMG>(D, pj, pi);
+      auto pair = [&](double4 pj, bool valid) {
+        Sep sh;
+        const Sep d = separation<IMG>(D, pj, pi, sh);
         const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
-        const R r2 = x * x + y * y + z * z;
+        // padding entries (the atom itself) are moved out of range
+        const R r2 = valid ? x * x + y * y + z * z : (R)1e30;
         const bool in = r2 < rc2;  // branch-free: pairs beyond r_c are masked
-        const R r = sqrt_r<R>(r2);
-        R tt;
-        const int k = tab_index_masked<R>(r, rih, rloh, g.nr, in, tt, oor);
-        const R* row = rtab + k * MD_RTAB_W;
-        const R vr = ((row[3] * tt + row[2]) * tt + row[1]) * tt + row[0];
-        rho += in ? vr : (R)0;
-        if (EV) {
-          const R vp = ((row[7] * tt + row[6]) * tt + row[5]) * tt + row[4];
-          phi += in ? vp : (R)0;
+        R vr, vp;
+        if constexpr (std::is_same<R, float>::value) {
+          // r^2 table: no square root; below the table shows in the smallest r^2
+          float tt;
+          const float* row = rtab + qtab_index(r2, qih, qloh, tt) * MD_RTAB_W;
+          vr = cubic(row, tt);
+          vp = EV ? cubic(row + 4, tt) : 0.0f;
+          min_r2 = fminf(min_r2, r2);
+        } else {
+          const R r = sqrt_r<R>(r2);
+          R tt;
+          const int k = tab_index_masked<R>(r, rih, rloh, g.nr, in, tt, oor);
+          const R* row = rtab + k * MD_RTAB_W;
+          vr = ((row[3] * tt + row[2]) * tt + row[1]) * tt + row[0];
+          vp = EV ? ((row[7] * tt + row[6]) * tt + row[5]) * tt + row[4] : (R)0;
         }
+        rho += in ? vr : (R)0;
+        if (EV) phi += in ? vp : (R)0;
       };
-      visit_list<LANES, U>(neigh, e0, stride, S.l, nn,
-                           [&](int j) { return load_xyz(pos, j); }, pair);
+      visit_list_pipe<LANES, U>(neigh, e0, stride, S.l, nn, i,
+                                [&](int j) { return load_xyz(pos, j); }, pair);
     };
     if (wimg) run(std::true_type{});
     else run(std::false_type{});
   }
+  if (std::is_same<R, float>::value && (double)min_r2 < g.q_lo) oor = true;
   rho = md_group_sum<LANES>(rho);
   if (i >= 0) {
     if (EV) e_acc += 0.5 * (double)phi;
@@ -359,24 +420,42 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_density(
   }
 }
 
+// The FP32 density kernel is held to 64 VGPRs: two 1024-thread blocks (each with
+// its 64 KB table in LDS) then share a CU.
+#define MD_EAM_DENSITY_ARGS(R)                                                                 \
+  md_batch b, double4 *pos, const int *__restrict__ neigh, const int *__restrict__ nneigh,   \
+      int npad, const R *__restrict__ rtab_g, const R *__restrict__ etab, TabGeom g, R rc2,  \
+      double *saved, double *partial, long long *ev, int ev_cap, md_ctl_dev *ctl
+template <int LANES, bool EV, bool TLDS>
+__global__ __launch_bounds__(FBLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))) void
+k_eam_density_f32(MD_EAM_DENSITY_ARGS(float)) {
+  eam_density_body<float, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
+                                           saved, partial, ev, ev_cap, ctl);
+}
+template <int LANES, bool EV, bool TLDS>
+__global__ __launch_bounds__(FBLOCK) void k_eam_density_f64(MD_EAM_DENSITY_ARGS(double)) {
+  eam_density_body<double, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
+                                            saved, partial, ev, ev_cap, ctl);
+}
+#undef MD_EAM_DENSITY_ARGS
+
 // ---------------------------------------------------------------------------
 // EAM pass 2: f_i = sum_j [phi'(r) + (F'_i + F'_j) rho'(r)] (r_j - r_i) / r,
 // virial, trailing kick and kinetic energy.
 // ---------------------------------------------------------------------------
 template <typename R, int LANES, bool EV, bool TLDS>
-__global__ __launch_bounds__(FBLOCK) void k_eam_force(
-    md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
-    const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, TabGeom g, R rc2,
-    R* force, double* vel, double inv_mass, double half_dt, const double* partial, long long* ev,
-    int ev_cap, md_ctl_dev* ctl) {
+__device__ __forceinline__ void eam_force_body(
+    const md_batch& b, const double4* __restrict__ pos, const int* __restrict__ neigh,
+    const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, const TabGeom& g,
+    R rc2, R* force, double* vel, double inv_mass, double half_dt, const double* partial,
+    long long* ev, int ev_cap, md_ctl_dev* ctl) {
   constexpr int U = 4;
   extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
   __shared__ double tsum[MD_EV_LEN * 16];
-  const R* ftab = TLDS ? stage_table<R, MD_FTAB_W>(ftab_g, g.nr, (R*)s_dyn) : ftab_g;
+  const R* ftab = TLDS ? stage_table<R, MD_FTAB_W>(ftab_g, pair_rows<R>(g), (R*)s_dyn) : ftab_g;
   const Slot S = force_slot<LANES>(b.n_tiles);
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // W xx yy zz xy xz yz, K
-  bool oor = false;
   R fx = 0, fy = 0, fz = 0;
   R w[6] = {0, 0, 0, 0, 0, 0};
   int i = -1, nn = 0, raw = 0;
@@ -395,38 +474,53 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_force(
     const double4 pi = pos[i];
     const R fpi = load_fp<R>(pi.w);
     const R rih = (R)g.r_inv_h, rloh = (R)(g.r_lo * g.r_inv_h);
+    const float qih = (float)g.q_inv_h, qloh = (float)(g.q_lo * g.q_inv_h);
     const uint32_t e0 = (uint32_t)i * LANES + S.l, stride = (uint32_t)npad * LANES;
     auto run = [&](auto img_tag) {
       constexpr bool IMG = decltype(img_tag)::value;
-      auto pair = [&](double4 pj) {
-        const Sep d = separation<IMG>(D, pj, pi);
+      auto pair = [&](double4 pj, bool valid) {
+        Sep sh;
+        const Sep d = separation<IMG>(D, pj, pi, sh);
         const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
         const R r2 = x * x + y * y + z * z;
-        const bool in = r2 < rc2;  // branch-free: pairs beyond r_c are masked
-        const R rinv = rsqrt_r<R>(r2);
-        const R r = r2 * rinv;
-        R tt;
-        const int k = tab_index_masked<R>(r, rih, rloh, g.nr, in, tt, oor);
-        const R* row = ftab + k * MD_FTAB_W;
-        const R dphi = (row[2] * tt + row[1]) * tt + row[0];
-        const R drho = (row[5] * tt + row[4]) * tt + row[3];
-        // force on i from j: s (r_j - r_i), s = [phi' + (F'_i + F'_j) rho'] / r
-        const R s0 = (dphi + (fpi + load_fp<R>(pj.w)) * drho) * rinv;
+        const bool in = valid && r2 < rc2;  // branch-free: pairs beyond r_c are masked
+        // s = [phi'(r) + (F'_i + F'_j) rho'(r)] / r; the force on i from j is s (r_j - r_i).
+        // (Pairs below the table are flagged by the density pass, which sees the same r.)
+        R s0;
+        if constexpr (std::is_same<R, float>::value) {
+          float tt;
+          const float* row = ftab + qtab_index(r2, qih, qloh, tt) * MD_FTAB_W;
+          s0 = cubic(row, tt) + (fpi + load_fp<R>(pj.w)) * cubic(row + 4, tt);
+        } else {
+          const R rinv = rsqrt_r<R>(r2);
+          const R r = r2 * rinv;
+          R tt;
+          bool below = false;
+          const int k = tab_index_masked<R>(r, rih, rloh, g.nr, in, tt, below);
+          const R* row = ftab + k * MD_FTAB_W;
+          const R dphi = (row[2] * tt + row[1]) * tt + row[0];
+          const R drho = (row[5] * tt + row[4]) * tt + row[3];
+          s0 = (dphi + (fpi + load_fp<R>(pj.w)) * drho) * rinv;
+        }
         const R s = in ? s0 : (R)0;
-        fx += s * x;
-        fy += s * y;
-        fz += s * z;
-        if (EV) {
-          w[0] -= s * x * x;
-          w[1] -= s * y * y;
-          w[2] -= s * z * z;
-          w[3] -= s * x * y;
-          w[4] -= s * x * z;
-          w[5] -= s * y * z;
+        const R px = s * x, py = s * y, pz = s * z;
+        fx += px;
+        fy += py;
+        fz += pz;
+        if (EV && IMG) {
+          // virial: W = sum_i x_i (x) F_i + 1/2 sum_ij c_ij (x) f_ij, c_ij the image
+          // shift of the pair (zero for pairs that do not cross the boundary)
+          const R cx = (R)sh.x, cy = (R)sh.y, cz = (R)sh.z;
+          w[0] += cx * px;
+          w[1] += cy * py;
+          w[2] += cz * pz;
+          w[3] += cx * py;
+          w[4] += cx * pz;
+          w[5] += cy * pz;
         }
       };
-      visit_list<LANES, U>(neigh, e0, stride, S.l, nn, [&](int j) { return load_rec(pos, j); },
-                           pair);
+      visit_list_pipe<LANES, U>(neigh, e0, stride, S.l, nn, i,
+                                [&](int j) { return load_rec(pos, j); }, pair);
     };
     if (wimg) run(std::true_type{});
     else run(std::false_type{});
@@ -434,13 +528,22 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_force(
   fx = md_group_sum<LANES>(fx);
   fy = md_group_sum<LANES>(fy);
   fz = md_group_sum<LANES>(fz);
-  if (i >= 0 && S.l == 0)
-    acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
   if (EV)
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] = 0.5 * (double)w[k];
-  if (__any(oor)) {
-    if ((threadIdx.x & (MD_WAVE - 1)) == 0) md_flag(ctl, MD_FLAG_TABLE_RANGE);
+  if (i >= 0 && S.l == 0) {
+    acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
+    if (EV) {
+      // x_i (x) F_i: the atom's position with its total force (FP64)
+      const double4 pi = load_xyz(pos, i);
+      const double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
+      acc[0] += pi.x * Fx;
+      acc[1] += pi.y * Fy;
+      acc[2] += pi.z * Fz;
+      acc[3] += pi.x * Fy;
+      acc[4] += pi.x * Fz;
+      acc[5] += pi.y * Fz;
+    }
   }
   if (EV) {
     double res;
@@ -458,6 +561,27 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_force(
     accumulate_record<TPB>(b, lb, nlb, tsum, ev + (size_t)(ctl->step % ev_cap) * b.n_rep * MD_EV_LEN);
   }
 }
+
+// One kernel per precision (their register budgets differ).  Holding the FP32
+// kernel to 64 VGPRs, so that two 1024-thread blocks share a CU, measured slower
+// (35 us against 31 us on 131k Cu): the gathers then contend for the L1.
+#define MD_EAM_FORCE_ARGS(R)                                                                     \
+  md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,                  \
+      const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, TabGeom g, R rc2, \
+      R *force, double *vel, double inv_mass, double half_dt, const double *partial,            \
+      long long *ev, int ev_cap, md_ctl_dev *ctl
+template <int LANES, bool EV, bool TLDS>
+__global__ __launch_bounds__(FBLOCK) void k_eam_force_f32(
+    MD_EAM_FORCE_ARGS(float)) {
+  eam_force_body<float, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
+                                         inv_mass, half_dt, partial, ev, ev_cap, ctl);
+}
+template <int LANES, bool EV, bool TLDS>
+__global__ __launch_bounds__(FBLOCK) void k_eam_force_f64(MD_EAM_FORCE_ARGS(double)) {
+  eam_force_body<double, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
+                                          inv_mass, half_dt, partial, ev, ev_cap, ctl);
+}
+#undef MD_EAM_FORCE_ARGS
 
 // One block: per-box sums of the LJ tile partials in fixed order, written as a
 // fixed-point record to ev[(step % ev_cap) * n_rep + rep].
@@ -523,7 +647,8 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
     auto run = [&](auto img_tag) {
       constexpr bool IMG = decltype(img_tag)::value;
       auto pair = [&](double4 pj) {
-        const Sep d = separation<IMG>(D, pj, pi);
+        Sep sh;
+        const Sep d = separation<IMG>(D, pj, pi, sh);
         const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
         const R r2 = x * x + y * y + z * z;
         if (r2 < rc2) {
@@ -608,6 +733,9 @@ void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_ta
   g.e_inv_h = 1.0 / p.emb.h;
   g.nr = p.rho.ncoef - 3;
   g.ne = p.emb.ncoef - 3;
+  const md_qgrid qg = md_qgrid_plan(&p);
+  g.q_lo = qg.q_lo;
+  g.q_inv_h = 1.0 / qg.h;
   const R rc2 = (R)(p.r_cut * p.r_cut);
   constexpr int TPB = Shape<LANES>::TPB;
   const dim3 grid(md_grid_blocks((b.n_tiles + TPB - 1) / TPB)), block(FBLOCK);
@@ -615,17 +743,28 @@ void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_ta
   const R* rtab = (const R*)(tab + TL.rtab);
   const R* ftab = (const R*)(tab + TL.ftab);
   const R* etab = (const R*)(tab + TL.etab);
-  const bool ld = table_in_lds<R>(g.nr, MD_RTAB_W);
-  const size_t lds_d = ld ? (size_t)g.nr * MD_RTAB_W * sizeof(R) : 0;
-  const size_t lds_f = ld ? (size_t)g.nr * MD_FTAB_W * sizeof(R) : 0;
+  const int rows = pair_rows<R>(g);
+  const bool ld = table_in_lds<R>(rows, MD_RTAB_W);
+  const size_t lds_d = ld ? (size_t)rows * MD_RTAB_W * sizeof(R) : 0;
+  const size_t lds_f = ld ? (size_t)rows * MD_FTAB_W * sizeof(R) : 0;
 #define MD_EAM_LAUNCH(EVB, TL_)                                                                 \
   do {                                                                                         \
-    MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density<R, LANES, EVB, TL_>), grid, block,    \
-                    lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g, rc2, \
-                    saved, partial, ev, ev_cap, ctl);                                          \
-    MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force<R, LANES, EVB, TL_>), grid, block, lds_f, \
-                    st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g, rc2,        \
-                    (R*)force, vel, inv_mass, half_dt, partial, ev, ev_cap, ctl);              \
+    if constexpr (std::is_same<R, float>::value)                                               \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f32<LANES, EVB, TL_>), grid, block, \
+                      lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
+                      rc2, saved, partial, ev, ev_cap, ctl);                                   \
+    else                                                                                       \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f64<LANES, EVB, TL_>), grid, block, \
+                      lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
+                      rc2, saved, partial, ev, ev_cap, ctl);                                   \
+    if constexpr (std::is_same<R, float>::value)                                               \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f32<LANES, EVB, TL_>), grid, block,     \
+                      lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
+                      rc2, (R*)force, vel, inv_mass, half_dt, partial, ev, ev_cap, ctl);       \
+    else                                                                                       \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f64<LANES, EVB, TL_>), grid, block,     \
+                      lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
+                      rc2, (R*)force, vel, inv_mass, half_dt, partial, ev, ev_cap, ctl);       \
   } while (0)
   if (ev) {
     if (ld) MD_EAM_LAUNCH(true, true);

@@ -46,7 +46,7 @@ __device__ __forceinline__ bool md_displacement_exceeded(const md_ctl_dev* ctl) 
 
 // Offsets of the workspace regions (bytes, 256-aligned).
 struct md_ws_layout {
-  size_t cell_of, src, counts, pos_s, vel_s, id_s, partial, total;
+  size_t cell_of, rank, src, sid, counts, pos_s, vel_s, id_s, partial, total;
 };
 
 static inline size_t md_align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -55,7 +55,9 @@ static inline md_ws_layout md_ws_plan(const md_batch* b) {
   md_ws_layout L;
   size_t n = (size_t)b->n_atoms, o = 0;
   L.cell_of = o; o = md_align256(o + 4 * n);
+  L.rank = o;    o = md_align256(o + 4 * n);
   L.src = o;     o = md_align256(o + 4 * n);
+  L.sid = o;     o = md_align256(o + 4 * n);
   L.counts = o;  o = md_align256(o + 4 * (size_t)(b->n_cells + 1));
   L.pos_s = o;   o = md_align256(o + 32 * n);
   L.vel_s = o;   o = md_align256(o + 24 * n);

@@ -42,9 +42,15 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double inv_w, int
 // ---------------------------------------------------------------------------
 // 1. wrap, cell index, histogram.
 // ---------------------------------------------------------------------------
+// Lanes below this one in mask m.
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_bin_count(md_batch b, int mode, double4* pos,
-                                                             int* cell_of, int* counts,
-                                                             md_ctl_dev* ctl) {
+                                                             int* cell_of, int* rank_of,
+                                                             int* counts, md_ctl_dev* ctl) {
   // The rebuild decision: every block reduces the displacement maxima of the last
   // drift itself (no cross-block communication); block 0 publishes it for the
   // other rebuild kernels of this call.
@@ -73,7 +79,29 @@ _Pragma("unroll")
     const int cell = D.cell_off + (c[0] * D.nc[1] + c[1]) * D.nc[2] + c[2];
     pos[i] = make_double4(x[0], x[1], x[2], p.w);
     cell_of[i] = cell;
-    atomicAdd(&counts[cell], 1);
+    // Histogram with one atomic per distinct cell of the wavefront (the atoms are
+    // still nearly in cell order from the last rebuild); each atom keeps the slot
+    // it got, so the scatter needs no atomics.  Slot order inside a cell is
+    // arbitrary here; the gather ranks by id.
+    const int lane = threadIdx.x & (MD_WAVE - 1);
+    bool done = false;
+    int rank = 0;
+    for (;;) {
+      const unsigned long long pend = __builtin_amdgcn_ballot_w64(!done);
+      if (pend == 0) break;
+      const int leader = __builtin_ctzll(pend);
+      const int lc = __shfl(cell, leader, MD_WAVE);
+      const bool mine = !done && cell == lc;
+      const unsigned long long m = __builtin_amdgcn_ballot_w64(mine);
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&counts[lc], (int)__popcll(m));
+      base = __shfl(base, leader, MD_WAVE);
+      if (mine) {
+        rank = base + lanes_below(m);
+        done = true;
+      }
+    }
+    rank_of[i] = rank;
   });
   if (bad) md_flag(ctl, bad);
 }
@@ -110,24 +138,27 @@ __global__ __launch_bounds__(1024) void k_bin_scan(int n_cells, int mode, int* c
   }
 }
 
-// 3. scatter atom indices into their cell segments (arbitrary order inside a cell).
+// 3. scatter atom indices (and their ids) into their cell segments, at the slots
+//    the histogram handed out.
 __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_bin_scatter(md_batch b, int mode,
-                                                               const int* cell_of, int* counts,
-                                                               const int* cell_start, int* src,
+                                                               const int* cell_of,
+                                                               const int* rank_of,
+                                                               const int* cell_start,
+                                                               const int* id, int* src, int* sid,
                                                                const md_ctl_dev* ctl) {
   if (skip_rebuild(mode, ctl)) return;
   FOR_ATOMS(b, i, T, {
-    const int c = cell_of[i];
-    const int k = atomicAdd(&counts[c], 1);
-    src[cell_start[c] + k] = i;
+    const int dst = cell_start[cell_of[i]] + rank_of[i];
+    src[dst] = i;
+    sid[dst] = id[i];
   });
 }
 
 // 4. order each cell by atom id (rank sort inside the cell segment) and gather
 //    the atom records into the sorted copies.
 __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_bin_gather(
-    md_batch b, int mode, const int* cell_of, int* counts, const int* cell_start, const int* src,
-    const double4* pos, const double* vel, const int* id, double4* pos_s, double* vel_s,
+    md_batch b, int mode, const int* cell_of, const int* cell_start, const int* src,
+    const int* sid, const double4* pos, const double* vel, double4* pos_s, double* vel_s,
     int* id_s, const md_ctl_dev* ctl) {
   if (skip_rebuild(mode, ctl)) return;
   const int n = b.n_atoms;
@@ -135,20 +166,15 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_bin_gather(
     const int a = src[slot];
     const int c = cell_of[a];
     const int beg = cell_start[c], end = cell_start[c + 1];
-    const int my = id[a];
-    int rank = 0;
-    for (int k = beg; k < end; ++k) {
-      const int o = src[k];
-      const int io = id[o];
-      rank += (io < my) || (io == my && o < a);
-    }
+    const int my = sid[slot];
+    int rank = 0;  // ids are unique: the rank by id is a permutation of the segment
+    for (int k = beg; k < end; ++k) rank += sid[k] < my;
     const int dst = beg + rank;
     pos_s[dst] = pos[a];
     vel_s[dst] = vel[a];
     vel_s[n + dst] = vel[n + a];
     vel_s[2 * n + dst] = vel[2 * n + a];
     id_s[dst] = my;
-    if (slot == beg) counts[c] = 0;
   });
 }
 
@@ -218,7 +244,39 @@ struct Cand {
   bool valid;
 };
 
+// Entry `slot` of atom ia: row slot / lanes, column ia * lanes + slot % lanes.
+// FAST: the whole list spans < 4 GiB and a row < 2^24 ints, so a 32-bit byte offset
+// from the atom's (wave-uniform) first entry addresses it.
+template <bool FAST>
+__device__ __forceinline__ int* entry(int* neigh, int ia, int slot, int lanes_log2,
+                                      unsigned row) {
+  const int lanes = 1 << lanes_log2;
+  int* at = neigh + (size_t)ia * lanes;
+  const unsigned q = (unsigned)slot >> lanes_log2, col = (unsigned)slot & (lanes - 1);
+  return FAST ? (int*)((char*)at + ((__umul24(q, row) + col) << 2)) : at + ((size_t)q * row + col);
+}
+
+
+// Candidate c against atom k of the cell (position in s_p, index ia).
 template <int MODE>
+__device__ __forceinline__ bool accept_pair(const Cand& c, double (*s_p)[MD_WAVE], int k, int ia,
+                                            const double* len, const double* inv, const int* per,
+                                            double rns2) {
+  double dx = c.x - s_p[0][k], dy = c.y - s_p[1][k], dz = c.z - s_p[2][k];
+  if (MODE == SHIFT) {
+    dx = dx - c.sx;
+    dy = dy - c.sy;
+    dz = dz - c.sz;
+  } else if (MODE == RINT) {
+    if (per[0]) dx = dx - len[0] * rint(dx * inv[0]);
+    if (per[1]) dy = dy - len[1] * rint(dy * inv[1]);
+    if (per[2]) dz = dz - len[2] * rint(dz * inv[2]);
+  }
+  const double r2 = (dx * dx + dy * dy) + dz * dz;
+  return c.valid & (c.j != ia) & (r2 < rns2);
+}
+
+template <int MODE, bool FAST>
 __device__ __forceinline__ void cell_lists(const md_domain& D, int a0, int na, int C,
                                            const int* s_beg, const int* s_start,
                                            const int* s_code, double (*s_p)[MD_WAVE],
@@ -227,7 +285,7 @@ __device__ __forceinline__ void cell_lists(const md_domain& D, int a0, int na, i
                                            double rns2, bool img, md_ctl_dev* ctl) {
   const int lane = threadIdx.x & (MD_WAVE - 1);
   const int lanes = 1 << lanes_log2;
-  const size_t row = (size_t)npad * lanes;
+  const unsigned row = (unsigned)npad * lanes;  // ints per list row
   double len[3], inv[3];
   int per[3];
 #pragma unroll
@@ -271,28 +329,23 @@ __device__ __forceinline__ void cell_lists(const md_domain& D, int a0, int na, i
     for (int v0 = 0; v0 < C; v0 += MD_WAVE) {
       const Cand c = nx;
       if (v0 + MD_WAVE < C) nx = make(v0 + MD_WAVE + lane);  // next chunk in flight
-      for (int k = 0; k < gc; ++k) {
-        const int ia = a0 + g0 + k;
-        double dx = c.x - s_p[0][k], dy = c.y - s_p[1][k], dz = c.z - s_p[2][k];
-        if (MODE == SHIFT) {
-          dx = dx - c.sx;
-          dy = dy - c.sy;
-          dz = dz - c.sz;
-        } else if (MODE == RINT) {
-          if (per[0]) dx = dx - len[0] * rint(dx * inv[0]);
-          if (per[1]) dy = dy - len[1] * rint(dy * inv[1]);
-          if (per[2]) dz = dz - len[2] * rint(dz * inv[2]);
-        }
-        const double r2 = (dx * dx + dy * dy) + dz * dz;
-        const bool ok = c.valid & (c.j != ia) & (r2 < rns2);
-        const unsigned long long m = __ballot(ok);
-        const int slot = __builtin_amdgcn_readlane(tot, k) +
-                         (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        if (ok && slot < max_neigh)
-          neigh[(size_t)(slot >> lanes_log2) * row + (size_t)ia * lanes + (slot & (lanes - 1))] =
-              c.j;
-        tot += lane == k ? (int)__popcll(m) : 0;
+      // two atoms per trip: their distance chains overlap
+      for (int k = 0; k < gc; k += 2) {
+        const int k1 = min(k + 1, gc - 1);  // gc odd: the last trip tests atom k twice
+        const bool ok0 = accept_pair<MODE>(c, s_p, k, a0 + g0 + k, len, inv, per, rns2);
+        const bool ok1 = accept_pair<MODE>(c, s_p, k1, a0 + g0 + k1, len, inv, per, rns2) &&
+                         k1 != k;
+        const unsigned long long m0 = __builtin_amdgcn_ballot_w64(ok0);
+        const unsigned long long m1 = __builtin_amdgcn_ballot_w64(ok1);
+        const int base0 = __builtin_amdgcn_readlane(tot, k);
+        const int base1 = __builtin_amdgcn_readlane(tot, k1);
+        const int slot0 = base0 + lanes_below(m0), slot1 = base1 + lanes_below(m1);
+        if (ok0 && slot0 < max_neigh)
+          *entry<FAST>(neigh, a0 + g0 + k, slot0, lanes_log2, row) = c.j;
+        if (ok1 && slot1 < max_neigh)
+          *entry<FAST>(neigh, a0 + g0 + k1, slot1, lanes_log2, row) = c.j;
+        tot = lane == k ? base0 + (int)__popcll(m0) : tot;
+        tot = lane == k1 && k1 != k ? base1 + (int)__popcll(m1) : tot;
       }
     }
     if (lane < gc) {
@@ -329,7 +382,8 @@ __global__ __launch_bounds__(CELL_BLOCK) void k_build(md_batch b, int mode,
     if (b.domains[mid].cell_off <= cell) lo = mid; else hi = mid - 1;
   }
   const md_domain& D = b.domains[lo];
-  const int a0 = cell_start[cell], na = cell_start[cell + 1] - a0;
+  const int a0 = __builtin_amdgcn_readfirstlane(cell_start[cell]);
+  const int na = __builtin_amdgcn_readfirstlane(cell_start[cell + 1]) - a0;
   if (na == 0) return;
   const int local = cell - D.cell_off;
   const int c2 = local % D.nc[2], c1 = (local / D.nc[2]) % D.nc[1], c0 = local / (D.nc[2] * D.nc[1]);
@@ -354,7 +408,7 @@ __global__ __launch_bounds__(CELL_BLOCK) void k_build(md_batch b, int mode,
     const int u = __shfl_up(incl, o, MD_WAVE);
     if (lane >= o) incl += u;
   }
-  const int C = __shfl(incl, 31, MD_WAVE);
+  const int C = __builtin_amdgcn_readlane(incl, 31);
   if (lane < 32) {
     s_beg[w][lane] = lane < 27 ? incl - cnt : C;
     s_start[w][lane] = start;
@@ -372,15 +426,22 @@ __global__ __launch_bounds__(CELL_BLOCK) void k_build(md_batch b, int mode,
       small |= D.nc[q] < 5;
     }
   }
-  if (small)
-    cell_lists<RINT>(D, a0, na, C, s_beg[w], s_start[w], s_code[w], s_p[w], pos, neigh, nneigh,
-                     max_neigh, lanes_log2, npad, rns2, img, ctl);
-  else if (img)
-    cell_lists<SHIFT>(D, a0, na, C, s_beg[w], s_start[w], s_code[w], s_p[w], pos, neigh, nneigh,
-                      max_neigh, lanes_log2, npad, rns2, img, ctl);
-  else
-    cell_lists<PLAIN>(D, a0, na, C, s_beg[w], s_start[w], s_code[w], s_p[w], pos, neigh, nneigh,
-                      max_neigh, lanes_log2, npad, rns2, img, ctl);
+  const bool fast = ((size_t)npad << lanes_log2) < ((size_t)1 << 24) &&
+                    (size_t)max_neigh * npad * sizeof(int) < ((size_t)1 << 32);
+  const int mode_ = small ? RINT : (img ? SHIFT : PLAIN);
+#define MD_CELL_LISTS(M, R24)                                                                   \
+  cell_lists<M, R24>(D, a0, na, C, s_beg[w], s_start[w], s_code[w], s_p[w], pos, neigh, nneigh, \
+                     max_neigh, lanes_log2, npad, rns2, img, ctl)
+  if (fast) {
+    if (mode_ == PLAIN) MD_CELL_LISTS(PLAIN, true);
+    else if (mode_ == SHIFT) MD_CELL_LISTS(SHIFT, true);
+    else MD_CELL_LISTS(RINT, true);
+  } else {
+    if (mode_ == PLAIN) MD_CELL_LISTS(PLAIN, false);
+    else if (mode_ == SHIFT) MD_CELL_LISTS(SHIFT, false);
+    else MD_CELL_LISTS(RINT, false);
+  }
+#undef MD_CELL_LISTS
 }
 
 }  // namespace
@@ -400,7 +461,9 @@ extern "C" int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos
   const md_ws_layout L = md_ws_plan(b);
   char* w = (char*)ws;
   int* cell_of = (int*)(w + L.cell_of);
+  int* rank_of = (int*)(w + L.rank);
   int* src = (int*)(w + L.src);
+  int* sid = (int*)(w + L.sid);
   int* counts = (int*)(w + L.counts);
   double4* pos_s = (double4*)(w + L.pos_s);
   double* vel_s = (double*)(w + L.vel_s);
@@ -409,16 +472,16 @@ extern "C" int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos
   hipStream_t st = (hipStream_t)stream;
   const dim3 grid(md_atom_grid(b->n_tiles)), block(MD_ATOM_BLOCK);
   MD_LAUNCH_TIMED(MD_KERNEL_BIN_COUNT, k_bin_count, grid, block, 0, st, *b, (int)mode,
-                  (double4*)pos, cell_of, counts, c);
+                  (double4*)pos, cell_of, rank_of, counts, c);
   MD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, b->n_cells, (int)mode, counts,
                      cell_start, c);
   MD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bin_scatter, grid, block, 0, st, *b, (int)mode, cell_of, counts,
-                     cell_start, src, c);
+  hipLaunchKernelGGL(k_bin_scatter, grid, block, 0, st, *b, (int)mode, cell_of, rank_of,
+                     cell_start, id, src, sid, c);
   MD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bin_gather, grid, block, 0, st, *b, (int)mode, cell_of, counts,
-                     cell_start, src, (const double4*)pos, vel, id, pos_s, vel_s, id_s, c);
+  hipLaunchKernelGGL(k_bin_gather, grid, block, 0, st, *b, (int)mode, cell_of, cell_start, src,
+                     sid, (const double4*)pos, vel, pos_s, vel_s, id_s, c);
   MD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_bin_copyback, grid, block, 0, st, *b, (int)mode, pos_s, vel_s, id_s,
                      (double4*)pos, vel, id, pos_ref, c);

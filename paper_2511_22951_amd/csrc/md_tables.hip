@@ -50,7 +50,7 @@ template <typename R>
 __global__ void k_eam_prepare(md_eam p, R* rtab, R* ftab, R* etab) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int nr = p.rho.ncoef - 3, ne = p.emb.ncoef - 3;
-  if (k < nr) {
+  if (rtab && k < nr) {
     double ar[4], ap[4];
     interval_poly(p.rho.coef + k, ar);
     interval_poly(p.phi.coef + k, ap);
@@ -75,12 +75,70 @@ __global__ void k_eam_prepare(md_eam p, R* rtab, R* ftab, R* etab) {
   }
 }
 
+// Value, first and second derivative in r of the B-spline (coefficients c,
+// breakpoints x_lo + k h, nint intervals) at r; the end intervals extend beyond.
+__device__ void spline_eval(const double* c, double x_lo, double h, int nint, double r,
+                            double& v, double& d1, double& d2) {
+  const double u = (r - x_lo) / h;
+  int k = (int)floor(u);
+  k = k < 0 ? 0 : (k > nint - 1 ? nint - 1 : k);
+  const double t = u - k;
+  double a[4];
+  interval_poly(c + k, a);
+  v = ((a[3] * t + a[2]) * t + a[1]) * t + a[0];
+  d1 = ((3.0 * a[3] * t + 2.0 * a[2]) * t + a[1]) / h;
+  d2 = (6.0 * a[3] * t + 2.0 * a[2]) / (h * h);
+}
+
+// Cubic in t on [0, 1] with values f0, f1 and t-derivatives g0, g1 at the ends.
+__device__ void hermite(double f0, double g0, double f1, double g1, float* a) {
+  a[0] = (float)f0;
+  a[1] = (float)g0;
+  a[2] = (float)(3.0 * (f1 - f0) - 2.0 * g0 - g1);
+  a[3] = (float)(2.0 * (f0 - f1) + g0 + g1);
+}
+
+// FP32 pair tables on the r^2 grid (one thread per interval).  At q = r^2:
+// d/dq s(r) = s'(r) / (2 r), and for G = s'(r) / r, dG/dq = (r s'' - s') / (2 r^3).
+__global__ void k_eam_prepare_q(md_eam p, double q_lo, double h_q, float* rtab, float* ftab) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= MD_STAB_N) return;
+  const int nr = p.rho.ncoef - 3;
+  double val[2][2], dq[2][2], G[2][2], dG[2][2];  // [end][phi, rho]
+  for (int e = 0; e < 2; ++e) {
+    const double q = q_lo + (k + e) * h_q, r = sqrt(q);
+    const md_spline* f[2] = {&p.phi, &p.rho};
+    for (int m = 0; m < 2; ++m) {
+      double v, d1, d2;
+      spline_eval(f[m]->coef, f[m]->x_lo, f[m]->h, nr, r, v, d1, d2);
+      val[e][m] = v;
+      dq[e][m] = d1 / (2.0 * r) * h_q;
+      G[e][m] = d1 / r;
+      dG[e][m] = (r * d2 - d1) / (2.0 * r * r * r) * h_q;
+    }
+  }
+  float* d = rtab + (size_t)k * MD_RTAB_W;
+  hermite(val[0][1], dq[0][1], val[1][1], dq[1][1], d);      // rho
+  hermite(val[0][0], dq[0][0], val[1][0], dq[1][0], d + 4);  // phi
+  float* f = ftab + (size_t)k * MD_FTAB_W;
+  hermite(G[0][0], dG[0][0], G[1][0], dG[1][0], f);      // phi' / r
+  hermite(G[0][1], dG[0][1], G[1][1], dG[1][1], f + 4);  // rho' / r
+}
+
 }  // namespace
+
+md_qgrid md_qgrid_plan(const md_eam* p) {
+  md_qgrid g;
+  g.q_lo = p->rho.x_lo * p->rho.x_lo;
+  g.h = (p->r_cut * p->r_cut - g.q_lo) / MD_STAB_N;
+  return g;
+}
 
 md_table_layout md_table_plan(const md_eam* p, md_precision prec) {
   md_table_layout L;
   const size_t es = prec == MD_FP32 ? 4 : 8;
-  const size_t nr = (size_t)(p->rho.ncoef - 3), ne = (size_t)(p->emb.ncoef - 3);
+  const size_t ne = (size_t)(p->emb.ncoef - 3);
+  const size_t nr = prec == MD_FP32 ? (size_t)MD_STAB_N : (size_t)(p->rho.ncoef - 3);
   L.rtab = 0;
   L.ftab = md_align256(nr * MD_RTAB_W * es);
   L.etab = L.ftab + md_align256(nr * MD_FTAB_W * es);
@@ -122,10 +180,16 @@ extern "C" int md_eam_prepare(const md_eam* p, md_precision prec, void* table, v
   const int n = p->rho.ncoef > p->emb.ncoef ? p->rho.ncoef : p->emb.ncoef;
   const dim3 grid((n + 255) / 256), block(256);
   char* t = (char*)table;
-  if (prec == MD_FP32)
+  if (prec == MD_FP32) {
+    // embedding rows from the rhobar spline; pair rows resampled on the r^2 grid
     hipLaunchKernelGGL(k_eam_prepare<float>, grid, block, 0, (hipStream_t)stream, *p,
-                       (float*)(t + L.rtab), (float*)(t + L.ftab), (float*)(t + L.etab));
-  else
+                       (float*)nullptr, (float*)nullptr, (float*)(t + L.etab));
+    MD_LAUNCH_CHECK();
+    const md_qgrid q = md_qgrid_plan(p);
+    hipLaunchKernelGGL(k_eam_prepare_q, dim3((MD_STAB_N + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, *p, q.q_lo, q.h, (float*)(t + L.rtab),
+                       (float*)(t + L.ftab));
+  } else
     hipLaunchKernelGGL(k_eam_prepare<double>, grid, block, 0, (hipStream_t)stream, *p,
                        (double*)(t + L.rtab), (double*)(t + L.ftab), (double*)(t + L.etab));
   MD_LAUNCH_CHECK();

@@ -4,6 +4,7 @@ Tolerances:
   neighbour sets, wrapped positions, cell order       bit-exact
   FP64 forces / energy / virial                       relative 1e-12 (Frobenius) / 1e-12 / 1e-11
   FP32 forces                                         relative 1e-5 (Frobenius, all atoms)
+  FP32 virial                                         1e-5 of the largest component
   FP32 energy                                         1e-6 eV per atom
 """
 import numpy as np
@@ -149,6 +150,7 @@ def test_eam_matches_oracle(mdmod, prec, lanes):
     else:
         assert rel_fro(st.forces(), r.force) < 1e-5
         assert abs(e[0] - r.energy) / len(pos) < 1e-6
+        assert np.max(np.abs(e[1:7] - r.virial)) < 1e-5 * np.max(np.abs(r.virial))
         assert np.max(np.abs(rb - r.rhobar)) < 1e-5 * np.max(r.rhobar)
 
 
