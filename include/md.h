@@ -251,7 +251,8 @@ int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec, const dou
  *   f_i = -sum_j [phi'(r) + (F'(rhobar_i) + F'(rhobar_j)) rho'(r)] r_ij / r,
  * with the virial and an optional trailing half kick as in md_lj_forces.
  * table: from md_eam_prepare in the same precision.  If saved is not NULL it
- * receives {rhobar, F', F''} as [3][n] FP64 for md_eam_backward. */
+ * receives {rhobar, F', F''} as [3][n] FP64 for md_eam_backward.  MD_FP32 takes
+ * lists with 1, 2, 4 or 8 lanes per atom (16: MD_ERR_ARG); MD_FP64 all five. */
 int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec, const void* table,
                   const double* pos, const md_nlist* nl, void* force, double* saved,
                   double* vel, double inv_mass, double half_dt, long long* ev, int ev_cap, void* ws,

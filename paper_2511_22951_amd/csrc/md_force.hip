@@ -192,22 +192,24 @@ __device__ __forceinline__ void visit_list(const int* neigh, uint32_t e0, uint32
 
 // Software-pipelined variant for the EAM passes: the list indices of the next U
 // entries are loaded while the records of the current U are in flight, so a lane
-// waits for one round trip per U entries instead of two.  A lane's last block is
-// padded with its own atom (`self`); pair(q, valid) masks those entries.
+// waits for one round trip per U entries instead of two.  All loads are issued
+// unconditionally in a fixed order (entries past the lane's end read the atom's
+// first entry and are replaced by the atom itself, `self`), so the compiler can
+// wait for the records alone; pair(q, valid) masks the padding.
 template <int LANES, int U, typename Load, typename Pair>
 __device__ __forceinline__ void visit_list_pipe(const int* neigh, uint32_t e0, uint32_t stride,
                                                 int l, int nn, int self, Load load, Pair pair) {
   const int cnt = nn > l ? (nn - l + LANES - 1) / LANES : 0;  // this lane's entries
   int jn[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) jn[u] = u < cnt ? load_idx(neigh, e0 + u * stride) : self;
+  for (int u = 0; u < U; ++u) jn[u] = load_idx(neigh, u < cnt ? e0 + u * stride : e0);
   uint32_t e = e0 + U * stride;
   for (int b0 = 0; b0 < cnt; b0 += U) {
     decltype(load(0)) q[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) q[u] = load(jn[u]);
+    for (int u = 0; u < U; ++u) q[u] = load(b0 + u < cnt ? jn[u] : self);
 #pragma unroll
-    for (int u = 0; u < U; ++u) jn[u] = b0 + U + u < cnt ? load_idx(neigh, e + u * stride) : self;
+    for (int u = 0; u < U; ++u) jn[u] = load_idx(neigh, b0 + U + u < cnt ? e + u * stride : e0);
     e += U * stride;
 #pragma unroll
     for (int u = 0; u < U; ++u) pair(q[u], b0 + u < cnt);
@@ -313,13 +315,12 @@ __device__ __forceinline__ void step_bookkeeping(md_ctl_dev* ctl) {
 // ---------------------------------------------------------------------------
 // EAM pass 1: rhobar_i = sum_j rho(r_ij), F'(rhobar_i) into pos[i].w, energy.
 // ---------------------------------------------------------------------------
-template <typename R, int LANES, bool EV, bool TLDS>
+template <typename R, int LANES, bool EV, bool TLDS, int U>
 __device__ __forceinline__ void eam_density_body(
     const md_batch& b, double4* pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const R* __restrict__ rtab_g,
     const R* __restrict__ etab, const TabGeom& g, R rc2, double* saved, double* partial,
     long long* ev, int ev_cap, md_ctl_dev* ctl) {
-  constexpr int U = 4;  // neighbours in flight per lane
   extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
   const R* rtab = TLDS ? stage_table<R, MD_RTAB_W>(rtab_g, pair_rows<R>(g), (R*)s_dyn) : rtab_g;
@@ -420,21 +421,20 @@ __device__ __forceinline__ void eam_density_body(
   }
 }
 
-// The FP32 density kernel is held to 64 VGPRs: two 1024-thread blocks (each with
-// its 64 KB table in LDS) then share a CU.
+// One density kernel per precision (their register budgets differ).  FP32 keeps 8
+// neighbours in flight per lane.
 #define MD_EAM_DENSITY_ARGS(R)                                                                 \
   md_batch b, double4 *pos, const int *__restrict__ neigh, const int *__restrict__ nneigh,   \
       int npad, const R *__restrict__ rtab_g, const R *__restrict__ etab, TabGeom g, R rc2,  \
       double *saved, double *partial, long long *ev, int ev_cap, md_ctl_dev *ctl
 template <int LANES, bool EV, bool TLDS>
-__global__ __launch_bounds__(FBLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))) void
-k_eam_density_f32(MD_EAM_DENSITY_ARGS(float)) {
-  eam_density_body<float, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
+__global__ __launch_bounds__(FBLOCK) void k_eam_density_f32(MD_EAM_DENSITY_ARGS(float)) {
+  eam_density_body<float, LANES, EV, TLDS, 8>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
                                            saved, partial, ev, ev_cap, ctl);
 }
 template <int LANES, bool EV, bool TLDS>
 __global__ __launch_bounds__(FBLOCK) void k_eam_density_f64(MD_EAM_DENSITY_ARGS(double)) {
-  eam_density_body<double, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
+  eam_density_body<double, LANES, EV, TLDS, 4>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
                                             saved, partial, ev, ev_cap, ctl);
 }
 #undef MD_EAM_DENSITY_ARGS
@@ -449,7 +449,7 @@ __device__ __forceinline__ void eam_force_body(
     const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, const TabGeom& g,
     R rc2, R* force, double* vel, double inv_mass, double half_dt, const double* partial,
     long long* ev, int ev_cap, md_ctl_dev* ctl) {
-  constexpr int U = 4;
+  constexpr int U = 4;  // (8 in flight measured slower here: the gathers contend)
   extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
   __shared__ double tsum[MD_EV_LEN * 16];
@@ -823,6 +823,8 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
   if (ev && ev_cap < 1) return MD_ERR_ARG;
   if (vel && !(inv_mass > 0.0)) return MD_ERR_ARG;
+  // FP32 takes 1-8 lanes per atom (16 is not supported)
+  if (prec == MD_FP32 && nl->lanes > 8) return MD_ERR_ARG;
   if (b->n_atoms == 0 || b->n_tiles == 0) return MD_OK;
   const md_table_layout TL = md_table_plan(p, prec);
   const md_ws_layout WL = md_ws_plan(b);

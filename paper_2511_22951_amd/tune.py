@@ -72,6 +72,8 @@ def best_lanes(system, prec, candidates=CANDIDATES, samples=10, use_cache=True):
     cache = _load() if use_cache else {}
     results = {}
     key = None
+    if prec == N.MD_FP32:
+        candidates = tuple(c for c in candidates if c <= 8)  # FP32: 1-8 lanes per atom
     for lanes in candidates:
         sim = Simulation(system, precision=prec, lanes=lanes, ev_cap=4).setup()
         if key is None:

@@ -154,6 +154,27 @@ def test_eam_matches_oracle(mdmod, prec, lanes):
         assert np.max(np.abs(rb - r.rhobar)) < 1e-5 * np.max(r.rhobar)
 
 
+@pytest.mark.skip(reason="FP32 at 16 lanes per atom on 19,652 atoms faulted the GPU on its first "
+                         "run; no cause was found by reading the code, so FP32 at 16 lanes is "
+                         "switched off (md_eam_forces returns MD_ERR_ARG) and this case stays off")
+def test_eam_fp32_large_batch_shape(mdmod):
+    """FP32 density/force on a system with more wavefronts than fit on the chip at once
+    at 16 lanes per atom (19,652 atoms): the kernels' other launch shape."""
+    tab = mi.tabulate_eam(mi.EAM_CU)
+    pos, box = displaced(17, 3.615, 0.05, seed=14)
+    plan, st, nl = _setup(mdmod, pos, box, 5.8, lanes=16, prec=1)
+    assert plan.n_tiles * 16 > 16 * 256
+    pot = mdmod.EAMPotential.from_table(tab)
+    ev = md_ev(1)
+    mdmod.md_eam_forces(st, pot, nl, ev=ev)
+    st.check_flags()
+    r = core.eam(pos, box, core.EAMPotential.from_table(tab))
+    e = evv(ev)[0, 0]
+    assert rel_fro(st.forces(), r.force) < 1e-5
+    assert abs(e[0] - r.energy) / len(pos) < 1e-6
+    assert np.max(np.abs(e[1:7] - r.virial)) < 1e-5 * np.max(np.abs(r.virial))
+
+
 def test_eam_table_range_flag(mdmod):
     """Atoms pushed closer than the table start set MD_FLAG_TABLE_RANGE."""
     tab = mi.tabulate_eam(mi.EAM_CU, r_lo=2.4)
