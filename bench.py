@@ -52,17 +52,23 @@ def parse():
                     help="cu131k: the headline EAM Cu NVE run; the others are the secondary "
                          "measurements (640k-atom Al shock, 64 batched cold-curve replicas, "
                          "force-matching epochs)")
+    ap.add_argument("--unfused", action="store_true",
+                    help="run the kick-drift as its own pass instead of fusing it into the force "
+                         "pass")
     ap.add_argument("--rebuild-every", type=int, default=-1,
                     help="rebuild period k (0: on the half-skin threshold every step; "
                          "-1: k chosen from the warm-up's rebuild intervals)")
     return ap.parse_args()
 
 
-def algorithmic_force_bytes(n_atoms, mean_neigh, force_bytes):
+def algorithmic_force_bytes(n_atoms, mean_neigh, force_bytes, fused=False):
     """EAM force pass, per atom: list length 4 B + list 4 B/entry + own record (x, y, z,
-    F') 32 B + force write 3 * force_bytes + velocity read and write 48 B (fused kick).
-    Neighbour records are gathered from cache (counted in the traffic measurement)."""
-    return n_atoms * (4.0 + 4.0 * mean_neigh + 32.0 + 3.0 * force_bytes + 48.0)
+    F') 32 B + force write 3 * force_bytes + velocity read and write 48 B (trailing kick);
+    with the next kick-drift fused in, also the displacement reference read 24 B and the
+    new position record written 32 B.  Neighbour records are gathered from cache (counted
+    in the traffic measurement)."""
+    extra = 56.0 if fused else 0.0
+    return n_atoms * (4.0 + 4.0 * mean_neigh + 32.0 + 3.0 * force_bytes + 48.0 + extra)
 
 
 FORCE_SOURCES = ("paper_2511_22951_amd/csrc/md_force.hip", "paper_2511_22951_amd/csrc/md_internal.h",
@@ -116,7 +122,8 @@ def run_path(system, prec, lanes, args):
     from paper_2511_22951_amd.sim import Simulation
 
     cap = args.warmup + args.steps + args.kernel_samples + 8
-    sim = Simulation(system, precision=prec, lanes=lanes, ev_cap=cap).setup()
+    sim = Simulation(system, precision=prec, lanes=lanes, ev_cap=cap,
+                     fused=not args.unfused).setup()
     torch.cuda.synchronize()
     f0 = sim.state.forces()
     # Warm-up on the threshold policy, recording when rebuilds happen; then rebuild every
@@ -155,7 +162,8 @@ def run_path(system, prec, lanes, args):
     slope = float(np.polyfit(tps - tps[0], etot, 1)[0])
     # live kernel timing of the EAM passes and the kick-drift kernel
     kt = {}
-    for kname in ("eam_force", "eam_density", "kick_drift", "build"):
+    knames = ("eam_force", "eam_density", "build") + (() if sim.fused else ("kick_drift",))
+    for kname in knames:
         if kname == "build":  # one rebuild per sample
             kt[kname] = time_kernel(N, kname, lambda: sim.rebuild(), max(3, args.kernel_samples // 10))
         else:
@@ -251,7 +259,7 @@ def main():
     value = n * args.steps / (R["ms"] * 1e-3)
     fb = 4 if head == "fp32" else 8
     kt_force = R["kernels_ms"]["eam_force"][0] * 1e-3
-    bytes_force = algorithmic_force_bytes(n, R["mean_neigh"], fb)
+    bytes_force = algorithmic_force_bytes(n, R["mean_neigh"], fb, fused=not args.unfused)
     achieved = bytes_force / kt_force / 1e9
 
     f_gpu = {k: r["f0"] for k, r in results.items()}
@@ -289,6 +297,7 @@ def main():
         paths[k] = {"atom_steps_per_s": n * args.steps / (r["ms"] * 1e-3),
                     "ms_per_step": r["ms"] / args.steps, "lanes": r["lanes"],
                     "rebuilds": r["rebuilds"], "mean_neigh": r["mean_neigh"],
+                    "kick_drift": "fused into the force pass" if not args.unfused else "own pass",
                     "rebuild_policy": ("every %d steps, half-skin criterion verified every step "
                                        "(no violation)" % r["rebuild_every"]
                                        if r["rebuild_every"] > 0 else "on the half-skin threshold"),
@@ -355,7 +364,7 @@ def bench_al_shock(args):
     lanes = args.lanes or autotune_lanes(system, N.MD_FP32)
     cap = args.warmup + steps + args.kernel_samples + 8
     sim = Simulation(system, precision=N.MD_FP32, lanes=lanes, max_neigh=160, ev_cap=cap,
-                     rebuild_every=0).setup()
+                     rebuild_every=0, fused=not args.unfused).setup()
     sim.run(args.warmup, graph_steps=args.graph_steps)
     torch.cuda.synchronize()
     st0 = sim.state.read_flags()[1]
@@ -363,13 +372,13 @@ def bench_al_shock(args):
     status, info = sim.state.read_flags()
     N.check(status, "device flags after the timed run")
     kt = {}
-    for kname in ("eam_force", "eam_density", "kick_drift"):
+    for kname in ("eam_force", "eam_density") + (() if sim.fused else ("kick_drift",)):
         kt[kname] = time_kernel(N, kname, lambda: sim.step(), args.kernel_samples)[0]
     nn = sim.nl.lengths().double()
     zc = sim.state.positions()[:, 2]
     rebuild_ms = _gpu_time(lambda: sim.rebuild(), 5) / 5
     kt_force = kt["eam_force"] * 1e-3
-    bytes_force = algorithmic_force_bytes(n, nn.mean().item(), 4)
+    bytes_force = algorithmic_force_bytes(n, nn.mean().item(), 4, fused=sim.fused)
     achieved = bytes_force / kt_force / 1e9
     out = {
         "metric": "atom-steps/s (EAM Al shock, FP32-mixed forces, FP64 integration)",

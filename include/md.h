@@ -246,16 +246,35 @@ int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec, const dou
                  const md_nlist* nl, void* force, double* vel, double inv_mass, double half_dt,
                  long long* ev, int ev_cap, void* ws, void* ctl, void* stream);
 
+/* The next step's kick-drift fused into the EAM force pass: after the trailing
+ * half kick of step n, v += dt/2 f/m and x_out = x + dt v with the walls at
+ * t = (step + 1) dt, then the half-skin displacement check against pos_ref --
+ * the same operations, in the same order, as md_verlet_step(MD_KICK_DRIFT) at
+ * the start of step n + 1 (Sec. 1.5), saving its pass over the atoms.  pos_out
+ * (double4 [n], device) must not be pos: other atoms still read pos in the same
+ * pass; the caller swaps the two buffers after the call.  Velocities are left at
+ * the half step n + 1/2; the record of step n holds the kinetic energy at v(n). */
+typedef struct md_drift {
+  double* pos_out;
+  const double* pos_ref; /* [3][n] */
+  double dt;
+  double half_skin;      /* < 0: no criterion */
+  md_walls walls;        /* walls.enabled = 0: none */
+} md_drift;
+
 /* EAM forces: a density pass (rhobar_i = sum_j rho(r_ij), F(rhobar_i),
  * F'(rhobar_i), the energy) then a force pass
  *   f_i = -sum_j [phi'(r) + (F'(rhobar_i) + F'(rhobar_j)) rho'(r)] r_ij / r,
  * with the virial and an optional trailing half kick as in md_lj_forces.
  * table: from md_eam_prepare in the same precision.  If saved is not NULL it
  * receives {rhobar, F', F''} as [3][n] FP64 for md_eam_backward.  MD_FP32 takes
- * lists with 1, 2, 4 or 8 lanes per atom (16: MD_ERR_ARG); MD_FP64 all five. */
+ * lists with 1, 2, 4 or 8 lanes per atom (16: MD_ERR_ARG); MD_FP64 all five.
+ * drift: NULL, or the next step's kick-drift to fuse (md_drift; requires vel and
+ * half_dt = dt / 2). */
 int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec, const void* table,
                   const double* pos, const md_nlist* nl, void* force, double* saved,
-                  double* vel, double inv_mass, double half_dt, long long* ev, int ev_cap, void* ws,
+                  double* vel, double inv_mass, double half_dt, const md_drift* drift,
+                  long long* ev, int ev_cap, void* ws,
                   void* ctl, void* stream);
 
 /* Velocity Verlet (Sec. 1.5).  MD_KICK_DRIFT: v += half_dt f/m; x += dt v; walls

@@ -70,6 +70,11 @@ class Walls(C.Structure):
                 ("piston_v", C.c_double), ("top", C.c_double)]
 
 
+class Drift(C.Structure):
+    _fields_ = [("pos_out", C.c_void_p), ("pos_ref", C.c_void_p), ("dt", C.c_double),
+                ("half_skin", C.c_double), ("walls", Walls)]
+
+
 _lib = None
 _vp, _i, _d, _sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
 _P = C.POINTER
@@ -88,7 +93,7 @@ _SIGS = {
     "md_lj_forces": (_i, [_P(Batch), _P(LJ), _i, _vp, _P(NList), _vp, _vp, _d, _d, _vp, _i, _vp,
                           _vp, _vp]),
     "md_eam_forces": (_i, [_P(Batch), _P(EAM), _i, _vp, _vp, _P(NList), _vp, _vp, _vp, _d, _d,
-                           _vp, _i, _vp, _vp, _vp]),
+                           _P(Drift), _vp, _i, _vp, _vp, _vp]),
     "md_verlet_step": (_i, [_P(Batch), _i, _d, _vp, _vp, _vp, _i, _d, _P(Walls), _vp, _d, _vp,
                             _vp]),
     "md_eam_backward": (_i, [_P(Batch), _P(EAM), _i, _vp, _P(NList), _vp, _vp, _vp, _vp, _vp,

@@ -443,12 +443,22 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_density_f64(MD_EAM_DENSITY_ARGS(
 // EAM pass 2: f_i = sum_j [phi'(r) + (F'_i + F'_j) rho'(r)] (r_j - r_i) / r,
 // virial, trailing kick and kinetic energy.
 // ---------------------------------------------------------------------------
+// The next step's kick-drift fused into the force pass (md_drift): new positions
+// go to pos_out (pos is still being read by other blocks), velocities advance to
+// the half step, and the block's displacement maximum is published.
+struct DriftArgs {
+  double4* pos_out;  // nullptr: no fused drift
+  const double* pos_ref;
+  double dt, thr2;
+  md_walls_dev w;
+};
+
 template <typename R, int LANES, bool EV, bool TLDS>
 __device__ __forceinline__ void eam_force_body(
     const md_batch& b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, const TabGeom& g,
-    R rc2, R* force, double* vel, double inv_mass, double half_dt, const double* partial,
-    long long* ev, int ev_cap, md_ctl_dev* ctl) {
+    R rc2, R* force, double* vel, double inv_mass, double half_dt, const DriftArgs& dr,
+    const double* partial, long long* ev, int ev_cap, md_ctl_dev* ctl) {
   constexpr int U = 4;  // (8 in flight measured slower here: the gathers contend)
   extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
@@ -531,8 +541,35 @@ __device__ __forceinline__ void eam_force_body(
   if (EV)
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] = 0.5 * (double)w[k];
+  double d2max = 0.0;
+  int bad = 0;
   if (i >= 0 && S.l == 0) {
-    acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
+    if (dr.pos_out) {
+      // trailing half kick of this step (kinetic energy from it), then the next
+      // step's kick and drift, the same operations as md_verlet_step(MD_KICK_DRIFT)
+      const int n = b.n_atoms;
+      force[i] = fx;
+      force[n + i] = fy;
+      force[2 * n + i] = fz;
+      const double c = half_dt * inv_mass * MD_ACCEL;
+      const double F[3] = {(double)fx, (double)fy, (double)fz};
+      double v[3] = {vel[i] + c * F[0], vel[n + i] + c * F[1], vel[2 * n + i] + c * F[2]};
+      acc[6] = 0.5 / (inv_mass * MD_ACCEL) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      v[0] = v[0] + c * F[0];
+      v[1] = v[1] + c * F[1];
+      v[2] = v[2] + c * F[2];
+      const double4 p = pos[i];
+      double x[3] = {p.x, p.y, p.z};
+      md_drift_atom(x, v, dr.dt, dr.w, (double)(ctl->step + 1) * dr.dt);
+      vel[i] = v[0];
+      vel[n + i] = v[1];
+      vel[2 * n + i] = v[2];
+      dr.pos_out[i] = make_double4(x[0], x[1], x[2], p.w);
+      if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) bad |= MD_FLAG_NONFINITE;
+      d2max = md_disp2(x, dr.pos_ref, i, n);
+    } else {
+      acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
+    }
     if (EV) {
       // x_i (x) F_i: the atom's position with its total force (FP64)
       const double4 pi = load_xyz(pos, i);
@@ -560,6 +597,7 @@ __device__ __forceinline__ void eam_force_body(
     __syncthreads();
     accumulate_record<TPB>(b, lb, nlb, tsum, ev + (size_t)(ctl->step % ev_cap) * b.n_rep * MD_EV_LEN);
   }
+  if (dr.pos_out) md_publish_dmax(d2max, bad, dr.thr2, ctl);
 }
 
 // One kernel per precision (their register budgets differ).  Holding the FP32
@@ -568,18 +606,18 @@ __device__ __forceinline__ void eam_force_body(
 #define MD_EAM_FORCE_ARGS(R)                                                                     \
   md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,                  \
       const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, TabGeom g, R rc2, \
-      R *force, double *vel, double inv_mass, double half_dt, const double *partial,            \
-      long long *ev, int ev_cap, md_ctl_dev *ctl
+      R *force, double *vel, double inv_mass, double half_dt, DriftArgs dr,                     \
+      const double *partial, long long *ev, int ev_cap, md_ctl_dev *ctl
 template <int LANES, bool EV, bool TLDS>
 __global__ __launch_bounds__(FBLOCK) void k_eam_force_f32(
     MD_EAM_FORCE_ARGS(float)) {
   eam_force_body<float, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
-                                         inv_mass, half_dt, partial, ev, ev_cap, ctl);
+                                         inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);
 }
 template <int LANES, bool EV, bool TLDS>
 __global__ __launch_bounds__(FBLOCK) void k_eam_force_f64(MD_EAM_FORCE_ARGS(double)) {
   eam_force_body<double, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
-                                          inv_mass, half_dt, partial, ev, ev_cap, ctl);
+                                          inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);
 }
 #undef MD_EAM_FORCE_ARGS
 
@@ -724,8 +762,8 @@ bool table_in_lds(int nrows, int width) {
 template <typename R, int LANES>
 void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_table_layout& TL,
                 const double* pos, const md_nlist& nl, void* force, double* saved, double* vel,
-                double inv_mass, double half_dt, long long* ev, int ev_cap, double* partial,
-                md_ctl_dev* ctl, hipStream_t st) {
+                double inv_mass, double half_dt, const DriftArgs& dr, long long* ev, int ev_cap,
+                double* partial, md_ctl_dev* ctl, hipStream_t st) {
   TabGeom g;
   g.r_lo = p.rho.x_lo;
   g.r_inv_h = 1.0 / p.rho.h;
@@ -760,11 +798,11 @@ void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_ta
     if constexpr (std::is_same<R, float>::value)                                               \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f32<LANES, EVB, TL_>), grid, block,     \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
-                      rc2, (R*)force, vel, inv_mass, half_dt, partial, ev, ev_cap, ctl);       \
+                      rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);   \
     else                                                                                       \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f64<LANES, EVB, TL_>), grid, block,     \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
-                      rc2, (R*)force, vel, inv_mass, half_dt, partial, ev, ev_cap, ctl);       \
+                      rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);   \
   } while (0)
   if (ev) {
     if (ld) MD_EAM_LAUNCH(true, true);
@@ -816,8 +854,8 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
 extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec,
                              const void* table, const double* pos, const md_nlist* nl,
                              void* force, double* saved, double* vel, double inv_mass,
-                             double half_dt, long long* ev, int ev_cap, void* ws, void* ctl,
-                             void* stream) {
+                             double half_dt, const md_drift* drift, long long* ev, int ev_cap,
+                             void* ws, void* ctl, void* stream) {
   if (!batch_ok(b) || !md_eam_ok(p) || !table || !pos || !nlist_ok(nl) || !force || !ws || !ctl)
     return MD_ERR_ARG;
   if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
@@ -825,6 +863,20 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   if (vel && !(inv_mass > 0.0)) return MD_ERR_ARG;
   // FP32 takes 1-8 lanes per atom (16 is not supported)
   if (prec == MD_FP32 && nl->lanes > 8) return MD_ERR_ARG;
+  DriftArgs dr{nullptr, nullptr, 0.0, -1.0, md_walls_dev{0, 2, 0.0, 0.0, 0.0}};
+  if (drift) {
+    if (!vel || !(half_dt > 0.0) || !drift->pos_out || !drift->pos_ref ||
+        drift->pos_out == pos || !isfinite(drift->dt) || half_dt != 0.5 * drift->dt)
+      return MD_ERR_ARG;
+    if (md_walls_load(&drift->walls, &dr.w) != MD_OK) return MD_ERR_ARG;
+    dr.pos_out = (double4*)drift->pos_out;
+    dr.pos_ref = drift->pos_ref;
+    dr.dt = drift->dt;
+    dr.thr2 = drift->half_skin < 0.0 ? -1.0 : drift->half_skin * drift->half_skin;
+    // one displacement slot per block of the force pass
+    const int tpb = FBLOCK / (64 * nl->lanes);
+    if (md_grid_blocks((b->n_tiles + tpb - 1) / tpb) > MD_MAX_ATOM_BLOCKS) return MD_ERR_ARG;
+  }
   if (b->n_atoms == 0 || b->n_tiles == 0) return MD_OK;
   const md_table_layout TL = md_table_plan(p, prec);
   const md_ws_layout WL = md_ws_plan(b);
@@ -833,12 +885,12 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   md_ctl_dev* c = (md_ctl_dev*)ctl;
   if (prec == MD_FP32) {
     MD_DISPATCH_LANES(nl->lanes, (launch_eam<float, L_>(*b, *p, (const char*)table, TL, pos, *nl,
-                                                        force, saved, vel, inv_mass, half_dt, (long long*)ev,
-                                                        ev_cap, partial, c, st)));
+                                                        force, saved, vel, inv_mass, half_dt, dr,
+                                                        (long long*)ev, ev_cap, partial, c, st)));
   } else {
     MD_DISPATCH_LANES(nl->lanes, (launch_eam<double, L_>(*b, *p, (const char*)table, TL, pos, *nl,
-                                                         force, saved, vel, inv_mass, half_dt, (long long*)ev,
-                                                         ev_cap, partial, c, st)));
+                                                         force, saved, vel, inv_mass, half_dt, dr,
+                                                         (long long*)ev, ev_cap, partial, c, st)));
   }
   MD_LAUNCH_CHECK();
   return MD_OK;

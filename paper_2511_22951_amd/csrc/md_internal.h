@@ -105,6 +105,82 @@ __device__ __forceinline__ int md_remap_stride(int nblocks, int k) {
 
 __device__ __forceinline__ void md_flag(md_ctl_dev* ctl, int bits) { atomicOr(&ctl->flags, bits); }
 
+// Walls of md_walls in kernel-argument form (enabled = 0: none).
+struct md_walls_dev {
+  int enabled, axis;
+  double z0, v, top;
+};
+
+static inline int md_walls_load(const md_walls* walls, md_walls_dev* w) {
+  *w = md_walls_dev{0, 2, 0.0, 0.0, 0.0};
+  if (walls && walls->enabled) {
+    if (walls->axis < 0 || walls->axis > 2) return MD_ERR_ARG;
+    *w = md_walls_dev{1, walls->axis, walls->piston_z0, walls->piston_v, walls->top};
+  }
+  return MD_OK;
+}
+
+// The drift of velocity Verlet for one atom: x <- x + dt v (x holds the old
+// position on entry), then the walls at t_new: a piston plane z0 + v_p t that
+// reflects specularly in its own frame, and a static top wall (Sec. 1.5).  Shared
+// by the kick-drift kernel and the force pass that fuses the next kick-drift, so
+// both give the same bits.
+__device__ __forceinline__ void md_drift_atom(double (&x)[3], double (&v)[3], double dt,
+                                              const md_walls_dev& w, double t_new) {
+  x[0] = x[0] + dt * v[0];
+  x[1] = x[1] + dt * v[1];
+  x[2] = x[2] + dt * v[2];
+  if (w.enabled) {
+    const int a = w.axis;
+    const double zp = w.z0 + w.v * t_new;
+    if (x[a] < zp) {
+      x[a] = 2.0 * zp - x[a];
+      v[a] = 2.0 * w.v - v[a];
+    }
+    if (x[a] > w.top) {
+      x[a] = 2.0 * w.top - x[a];
+      v[a] = -v[a];
+    }
+  }
+}
+
+// |x - x_ref|^2 for the half-skin criterion; NaN counts as infinite (a rebuild,
+// and the non-finite flag is raised by the caller).
+__device__ __forceinline__ double md_disp2(const double (&x)[3], const double* pos_ref, int i,
+                                           int n) {
+  const double dx = x[0] - pos_ref[i], dy = x[1] - pos_ref[n + i], dz = x[2] - pos_ref[2 * n + i];
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  return d2 >= 0.0 ? d2 : INFINITY;
+}
+
+// Publish a block's displacement maximum (all threads call; blockDim <= 1024).
+// Block 0 also sets the fields the next step's rebuild and force kernels read.
+__device__ __forceinline__ void md_publish_dmax(double d2max, int bad, double thr2,
+                                                md_ctl_dev* ctl) {
+  __shared__ double s_dmax[16];
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) d2max = fmax(d2max, __shfl_xor(d2max, o, 64));
+  if (__any(bad)) {
+    int all = bad;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) all |= __shfl_xor(all, o, 64);
+    if (lane == 0) md_flag(ctl, all);
+  }
+  if (lane == 0) s_dmax[threadIdx.x / 64] = d2max;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = s_dmax[0];
+    for (int k = 1; k < (int)(blockDim.x / 64); ++k) m = fmax(m, s_dmax[k]);
+    ctl->dmax[blockIdx.x] = m;
+    if (blockIdx.x == 0) {  // fields no block of the publishing kernel reads
+      ctl->n_dmax = gridDim.x;
+      ctl->thr2 = thr2;
+      ctl->step_next = ctl->step + 1;
+    }
+  }
+}
+
 // Butterfly sum over the whole wavefront; every lane ends with the same value
 // (each stage adds a commutative pair, so all lanes round identically).
 template <typename T>

@@ -6,18 +6,12 @@
 
 namespace {
 
-struct Walls {
-  int enabled, axis;
-  double z0, v, top;
-};
-
 // v += dt/2 f/m; x += dt v; walls at t = (step + 1) dt; per-block maximum of
 // |x - x_ref|^2 into ctl->dmax[blockIdx.x].
 template <typename R>
 __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_kick_drift(
     md_batch b, double dt, double half_dt, double4* pos, double* vel, const R* force,
-    double inv_mass, Walls w, const double* pos_ref, double thr2, md_ctl_dev* ctl) {
-  __shared__ double sh[MD_ATOM_BLOCK / MD_WAVE];
+    double inv_mass, md_walls_dev w, const double* pos_ref, double thr2, md_ctl_dev* ctl) {
   const int nlb = (b.n_tiles + 3) / 4;
   const int lane = threadIdx.x & (MD_WAVE - 1);
   const int n = b.n_atoms;
@@ -36,49 +30,16 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_kick_drift(
     double v[3] = {vel[i] + c * (double)force[i], vel[n + i] + c * (double)force[n + i],
                    vel[2 * n + i] + c * (double)force[2 * n + i]};
     const double4 p = pos[i];
-    double x[3] = {p.x + dt * v[0], p.y + dt * v[1], p.z + dt * v[2]};
-    if (w.enabled) {
-      const int a = w.axis;
-      const double zp = w.z0 + w.v * t_new;
-      if (x[a] < zp) {  // specular reflection in the piston frame
-        x[a] = 2.0 * zp - x[a];
-        v[a] = 2.0 * w.v - v[a];
-      }
-      if (x[a] > w.top) {
-        x[a] = 2.0 * w.top - x[a];
-        v[a] = -v[a];
-      }
-    }
+    double x[3] = {p.x, p.y, p.z};
+    md_drift_atom(x, v, dt, w, t_new);
     vel[i] = v[0];
     vel[n + i] = v[1];
     vel[2 * n + i] = v[2];
     pos[i] = make_double4(x[0], x[1], x[2], p.w);
     if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) bad |= MD_FLAG_NONFINITE;
-    const double dx = x[0] - pos_ref[i], dy = x[1] - pos_ref[n + i], dz = x[2] - pos_ref[2 * n + i];
-    double d2 = dx * dx + dy * dy + dz * dz;
-    if (!(d2 >= 0.0)) d2 = INFINITY;  // NaN forces a rebuild (and is flagged)
-    d2max = fmax(d2max, d2);
+    d2max = fmax(d2max, md_disp2(x, pos_ref, i, n));
   }
-#pragma unroll
-  for (int o = MD_WAVE / 2; o > 0; o >>= 1) d2max = fmax(d2max, __shfl_xor(d2max, o, MD_WAVE));
-  if (__any(bad)) {
-    int all = bad;
-#pragma unroll
-    for (int o = MD_WAVE / 2; o > 0; o >>= 1) all |= __shfl_xor(all, o, MD_WAVE);
-    if (lane == 0) md_flag(ctl, all);
-  }
-  if (lane == 0) sh[threadIdx.x / MD_WAVE] = d2max;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = sh[0];
-    for (int k = 1; k < MD_ATOM_BLOCK / MD_WAVE; ++k) m = fmax(m, sh[k]);
-    ctl->dmax[blockIdx.x] = m;
-    if (blockIdx.x == 0) {  // fields no block of this kernel reads
-      ctl->n_dmax = gridDim.x;
-      ctl->thr2 = thr2;
-      ctl->step_next = ctl->step + 1;
-    }
-  }
+  md_publish_dmax(d2max, bad, thr2, ctl);
 }
 
 template <typename R>
@@ -124,15 +85,8 @@ extern "C" int md_verlet_step(const md_batch* b, md_verlet_phase phase, double d
     return MD_OK;
   }
   if (phase != MD_KICK_DRIFT || !pos || !pos_ref || !ctl) return MD_ERR_ARG;
-  Walls w{0, 2, 0.0, 0.0, 0.0};
-  if (walls && walls->enabled) {
-    if (walls->axis < 0 || walls->axis > 2) return MD_ERR_ARG;
-    w.enabled = 1;
-    w.axis = walls->axis;
-    w.z0 = walls->piston_z0;
-    w.v = walls->piston_v;
-    w.top = walls->top;
-  }
+  md_walls_dev w;
+  if (md_walls_load(walls, &w) != MD_OK) return MD_ERR_ARG;
   const double thr2 = half_skin < 0.0 ? -1.0 : half_skin * half_skin;
   md_ctl_dev* c = (md_ctl_dev*)ctl;
   if (prec == MD_FP32)

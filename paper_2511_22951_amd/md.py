@@ -277,14 +277,24 @@ def md_lj_forces(st: State, p, nl: NeighborList, inv_mass=0.0, half_dt=0.0, kick
                                _stream(stream)), "md_lj_forces")
 
 
+def drift_params(pos_out, pos_ref, dt, half_skin, walls=None):
+    """md_drift: the next step's kick-drift to fuse into md_eam_forces."""
+    w = walls_params(walls) if isinstance(walls, dict) else walls
+    return N.Drift(_ptr(pos_out), _ptr(pos_ref), float(dt), float(half_skin),
+                   w if w is not None else N.Walls(0, 2, 0.0, 0.0, 0.0))
+
+
 def md_eam_forces(st: State, pot: EAMPotential, nl: NeighborList, table=None, saved=None,
-                  inv_mass=0.0, half_dt=0.0, kick=False, ev=None, ev_cap=1, stream=None):
+                  inv_mass=0.0, half_dt=0.0, kick=False, ev=None, ev_cap=1, drift=None,
+                  stream=None):
     table = pot.table(st.precision) if table is None else table
     vel = st.vel if kick else None
     check(N.lib().md_eam_forces(C.byref(st.plan.c), C.byref(pot.c), st.precision, _ptr(table),
                                 _ptr(st.pos), C.byref(nl.c), _ptr(st.force), _ptr(saved),
-                                _ptr(vel), float(inv_mass), float(half_dt), _ptr(ev), int(ev_cap),
-                                _ptr(st.ws), _ptr(st.ctl), _stream(stream)), "md_eam_forces")
+                                _ptr(vel), float(inv_mass), float(half_dt),
+                                C.byref(drift) if drift is not None else None, _ptr(ev),
+                                int(ev_cap), _ptr(st.ws), _ptr(st.ctl), _stream(stream)),
+          "md_eam_forces")
 
 
 def md_verlet_step(st: State, phase, dt, inv_mass, walls=None, half_skin=-1.0, stream=None):

@@ -7,6 +7,13 @@ One step, all on one stream, no host synchronisation:
   md_bin_cells, md_build_neighbors    rebuild (policy below)
   md_eam_forces / md_lj_forces        forces, energy, virial, trailing kick v += dt/2 f/m
 
+With fused=True (EAM) the force pass also performs the next step's kick-drift
+(md_drift), writing the new positions into a second buffer that becomes current
+after the call, so from the second step on a step is rebuild + density + force.
+The arithmetic is the same, bit for bit; between steps the state is then one
+kick-drift ahead: positions x(n + 1), velocities v(n + 1/2) (`previous_positions`
+returns x(n)).
+
 Rebuild policies (both in the paper):
   rebuild_every = 0: on the threshold (Sec. 1.4) -- the rebuild kernels run every
       step in MD_IF_FLAGGED mode and do work only when an atom moved > skin/2;
@@ -17,6 +24,8 @@ Rebuild policies (both in the paper):
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import torch
 
@@ -26,8 +35,11 @@ from . import md
 
 class Simulation:
     def __init__(self, system, precision=N.MD_FP64, lanes=4, max_neigh=128, ev_cap=1024,
-                 device="cuda", table=None, rebuild_every=0):
+                 device="cuda", table=None, rebuild_every=0, fused=False):
         self.sys = system
+        self.fused = bool(fused) and system.potential != "lj"
+        self.primed = False  # fused: the last force pass already did the next kick-drift
+        self.pos_alt = None
         self.rebuild_every = int(rebuild_every)
         self.n_steps = 0
         self.precision = precision
@@ -85,7 +97,9 @@ class Simulation:
 
     def step(self, ev=True):
         st = self.state
-        md.md_verlet_step(st, N.MD_KICK_DRIFT, self.dt, self.inv_mass, self.walls, self.half_skin)
+        if not self.primed:
+            md.md_verlet_step(st, N.MD_KICK_DRIFT, self.dt, self.inv_mass, self.walls,
+                              self.half_skin)
         k = self.rebuild_every
         if k <= 0:
             md.md_bin_cells(st, N.MD_IF_FLAGGED)
@@ -93,17 +107,38 @@ class Simulation:
         elif (self.n_steps + 1) % k == 0:
             md.md_bin_cells(st, N.MD_ALWAYS)
             md.md_build_neighbors(st, self.nl, N.MD_ALWAYS)
-        self.forces(kick=True, ev=ev)
+        if self.fused:
+            if self.pos_alt is None:
+                self.pos_alt = torch.empty_like(st.pos)
+            drift = md.drift_params(self.pos_alt, st.pos_ref, self.dt, self.half_skin,
+                                    self.walls)
+            md.md_eam_forces(st, self.pot, self.nl, self.table, None, self.inv_mass,
+                             0.5 * self.dt, kick=True, ev=self.ev if ev else None,
+                             ev_cap=self.ev_cap, drift=drift)
+            st.pos, self.pos_alt = self.pos_alt, st.pos
+            self.primed = True
+        else:
+            self.forces(kick=True, ev=ev)
         self.n_steps += 1
+
+    def previous_positions(self):
+        """Fused mode: positions at the last completed step (x(n)), by original id."""
+        if not (self.fused and self.primed):
+            return self.state.positions()
+        return self.pos_alt[:, :3].cpu().numpy()[self.state._order()]
 
     # -- graphs ---------------------------------------------------------------
     def capture(self, steps, ev=True):
         """Capture `steps` consecutive steps into one graph (for rebuild_every = k the graph
-        must start at a multiple of k and span a multiple of k steps)."""
+        must start at a multiple of k and span a multiple of k steps; in fused mode it must
+        span an even number of steps, after at least one step, so that the two position
+        buffers are back in place at the end of each replay)."""
         k = self.rebuild_every
         if k > 0 and (steps % k or self.n_steps % k):
             raise ValueError("graph of %d steps at step %d does not align with rebuilds every %d"
                              % (steps, self.n_steps, k))
+        if self.fused and (steps % 2 or not self.primed):
+            raise ValueError("fused mode: graphs span an even number of steps, after the first")
         n0 = self.n_steps
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -118,7 +153,16 @@ class Simulation:
 
     def run(self, n_steps, graph_steps=0, ev=True):
         k = self.rebuild_every
-        if k > 0 and graph_steps:
+        if self.fused and graph_steps:
+            if not self.primed and n_steps > 0:
+                self.step(ev)
+                n_steps -= 1
+            period = 2 * k // math.gcd(2, k) if k > 0 else 2
+            graph_steps = max(period, graph_steps // period * period)
+            while n_steps > 0 and k > 0 and self.n_steps % k:  # align to the rebuild period
+                self.step(ev)
+                n_steps -= 1
+        elif k > 0 and graph_steps:
             graph_steps = max(k, graph_steps // k * k)
             while n_steps > 0 and self.n_steps % k:  # align to the rebuild period
                 self.step(ev)

@@ -276,6 +276,46 @@ def test_fixed_interval_rebuilds_match_oracle(mdmod):
     assert np.max(np.abs(e[:, 0] - hist[:, 1])) < 1e-10 * abs(hist[0, 1])
 
 
+@pytest.mark.parametrize("prec,policy", [(0, 0), (1, 6), (0, 6)])
+def test_fused_kick_drift_equals_separate(mdmod, prec, policy):
+    """The force pass with the next kick-drift fused in (md_drift) gives the same bits as the
+    separate md_verlet_step: EAM Cu, 30 steps, threshold rebuilds or rebuilds every 6 steps
+    with graph replay; the fused run is one kick-drift ahead at the end."""
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.eam_copper(cells=6)
+    a = Simulation(s, precision=prec, lanes=4, rebuild_every=policy).setup()
+    b = Simulation(s, precision=prec, lanes=4, rebuild_every=policy, fused=True).setup()
+    a.run(30, graph_steps=6 if policy else 0)
+    b.run(30, graph_steps=6 if policy else 0)
+    ia, ib = a.state.check_flags(), b.state.check_flags()
+    assert ia["n_rebuilds"] == ib["n_rebuilds"] > 1
+    assert np.array_equal(b.previous_positions(), a.state.positions())
+    assert np.array_equal(a.energies(range(31)), b.energies(range(31)))
+    mdmod.md_verlet_step(a.state, N.MD_KICK_DRIFT, a.dt, a.inv_mass, a.walls, a.half_skin)
+    assert np.array_equal(a.state.positions(), b.state.positions())
+    assert np.array_equal(a.state.velocities(), b.state.velocities())
+
+
+def test_fused_kick_drift_with_walls(mdmod):
+    """Fused kick-drift with the piston and top wall (the shock set-up) equals the separate
+    one bit for bit."""
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.eam_aluminum_shock(nx=4, ny=4, nz=8)
+    s.walls = dict(s.walls, piston_z0=0.6, piston_v=20.0)
+    a = Simulation(s, precision=1, lanes=4).setup()
+    b = Simulation(s, precision=1, lanes=4, fused=True).setup()
+    a.run(40)
+    b.run(40)
+    a.state.check_flags()
+    b.state.check_flags()
+    assert np.max(b.state.velocities()[:, 2]) > 30.0
+    mdmod.md_verlet_step(a.state, N.MD_KICK_DRIFT, a.dt, a.inv_mass, a.walls, a.half_skin)
+    assert np.array_equal(a.state.positions(), b.state.positions())
+    assert np.array_equal(a.state.velocities(), b.state.velocities())
+
+
 def test_stale_list_is_detected(mdmod):
     """Without rebuilds a hot system soon moves atoms by more than half the skin: the force
     pass reports MD_ERR_STALE_LIST."""
