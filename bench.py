@@ -224,7 +224,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print("bench.py: this build targets one GPU; --gpus %d is not supported (run with "
+        print("bench.py: this benchmark runs on one GPU; --gpus %d is not supported (run with "
               "--gpus 1)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "cu131k" and args.steps is None:
