@@ -47,11 +47,12 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device a few times (the known-size "
                          "transfer that scales the FETCH_SIZE/WRITE_SIZE counters)")
-    ap.add_argument("--workload", choices=["cu131k", "al_shock", "cold_curve", "force_matching"],
+    ap.add_argument("--workload", choices=["cu131k", "al_shock", "cold_curve", "force_matching",
+                                           "lj13m"],
                     default="cu131k",
                     help="cu131k: the headline EAM Cu NVE run; the others are the secondary "
                          "measurements (640k-atom Al shock, 64 batched cold-curve replicas, "
-                         "force-matching epochs)")
+                         "force-matching epochs, the 13M-atom LJ test of Sec. 1.7)")
     ap.add_argument("--unfused", action="store_true",
                     help="run the kick-drift as its own pass instead of fusing it into the force "
                          "pass")
@@ -252,7 +253,7 @@ def main():
         args.steps = 1000
     if args.workload != "cu131k":
         {"al_shock": bench_al_shock, "cold_curve": bench_cold_curve,
-         "force_matching": bench_force_matching}[args.workload](args)
+         "force_matching": bench_force_matching, "lj13m": bench_lj_paper}[args.workload](args)
         return
     import torch
     import mdinputs as mi
@@ -423,6 +424,89 @@ def bench_al_shock(args):
         "rebuild_us": 1e3 * rebuild_ms,
         "cpu_baseline": None,
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_lj_paper(args):
+    """The LJ performance test of Sec. 1.7 at its size on one GPU: 12,967,168 Ar atoms
+    (periodic fcc 148^3, small perturbations), 300 steps, lists rebuilt every 10 steps;
+    FP64 and FP32-mixed paths, both with HIP-graph replay."""
+    import torch
+    import mdinputs as mi
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    N.lib()
+    system = mi.lj_argon_benchmark()
+    n = system.pos.shape[0]
+    steps = args.steps or system.n_steps
+    k = system.extra["rebuild_every"]
+    gs = max(k, args.graph_steps // k * k)
+    warm = max(k, args.warmup // k * k)
+    sample = np.random.default_rng(7).choice(n, 256, replace=False)
+    paths, f_gpu = {}, {}
+    for name, prec in (("fp32", N.MD_FP32), ("fp64", N.MD_FP64)):
+        if args.precision not in ("both", name):
+            continue
+        lanes = args.lanes or autotune_lanes(system, prec)
+        cap = warm + steps + args.kernel_samples + 8
+        sim = Simulation(system, precision=prec, lanes=lanes, max_neigh=112, ev_cap=cap,
+                         rebuild_every=k).setup()
+        f_gpu[name] = sim.state.forces()[sample]
+        sim.run(warm, graph_steps=gs)
+        torch.cuda.synchronize()
+        st0 = sim.state.read_flags()[1]
+        ms = _gpu_time(lambda: sim.run(steps, graph_steps=gs), 1)
+        status, info = sim.state.read_flags()
+        N.check(status, "device flags after the timed run")
+        ev = sim.energies(range(st0["step"], info["step"] + 1))
+        etot = (ev[:, 0] + ev[:, 7]) / n
+        kt = {kn: 1e3 * time_kernel(N, kn, lambda: sim.step(), args.kernel_samples // 5)[0]
+              for kn in ("lj", "kick_drift")}
+        kt["build"] = 1e3 * time_kernel(N, "build", lambda: sim.rebuild(), 3)[0]
+        nn = sim.nl.lengths().double()
+        force_bytes = 4 if prec == N.MD_FP32 else 8
+        per_atom = 4.0 + 4.0 * nn.mean().item() + 32.0 + 3.0 * force_bytes + 48.0
+        paths[name] = {
+            "atom_steps_per_s": n * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+            "lanes": lanes, "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"],
+            "mean_neigh": nn.mean().item(), "max_neigh": int(nn.max().item()),
+            "energy_span_eV_per_atom": float(etot.max() - etot.min()),
+            "kernel_us": kt, "lj_bytes_per_launch": n * per_atom,
+            "lj_achieved_GBs": n * per_atom / (kt["lj"] * 1e-6) / 1e9,
+        }
+        del sim
+        torch.cuda.empty_cache()
+    head = paths.get("fp32") or paths["fp64"]
+    out = {
+        "metric": "atom-steps/s (LJ, 300 steps, lists rebuilt every 10 steps)",
+        "value": head["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if "fp32" in paths else "f64", "data": "synthetic",
+        "config": {"workload": "LJ Ar fcc 148^3 = 12967168 atoms, a 5.26, N(0, 0.05^2) "
+                               "displacements, 100 K, dt 2 fs, r_c 2.5 sigma, skin 0.5, "
+                               "rebuild every 10 steps", "n_atoms": n, "graph_steps": gs},
+        "roofline": {"bound": "hbm", "achieved": head["lj_achieved_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": head["lj_achieved_GBs"] / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": "k_lj", "kernel_us": head["kernel_us"]["lj"],
+                     "bytes_per_launch": head["lj_bytes_per_launch"]},
+        "paths": paths,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import core
+        lj = system.lj
+        t0 = time.perf_counter()
+        r = core.lj_sampled(system.pos, system.box, lj.eps, lj.sigma, lj.r_cut, sample)
+        dt = time.perf_counter() - t0
+        for name, f in f_gpu.items():
+            paths[name]["force_rel_err_vs_oracle_sampled"] = float(
+                np.linalg.norm(f - r.force) / np.linalg.norm(r.force))
+        out["cpu_baseline"] = {
+            "value": len(sample) / dt, "unit": "atom-steps/s (forces only)",
+            "cores": core.num_threads(), "kind": "oracle",
+            "sample": "FP64 O(N) force sums of %d sampled atoms over all %d atoms, %.1f s"
+                      % (len(sample), n, dt)}
     print(json.dumps(out), flush=True)
 
 

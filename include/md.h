@@ -174,7 +174,10 @@ typedef struct md_walls {
 
 /* Count the cells and tiles a batch needs.  Host arrays: boxes[n_rep],
  * atom_off[n_rep + 1].  Returns MD_ERR_BOX if a periodic length is not above
- * 2 r_ns (the minimum image of every neighbour must be unique). */
+ * 2 r_ns (the minimum image of every neighbour must be unique), MD_ERR_ARG if
+ * the batch holds more than MD_MAX_ATOMS atoms (the passes address the 32-byte
+ * position records with 32-bit byte offsets). */
+#define MD_MAX_ATOMS ((1 << 27) - 64)
 int md_plan_count(int n_rep, const md_box* boxes, const int* atom_off, double r_ns,
                   int tile_atoms, int* n_cells, int* n_tiles);
 

@@ -191,6 +191,20 @@ def lj_argon(cells: int = 4, seed: int | None = None) -> MDSystem:
                     2e-3, 100, 0.3, "lj", lj=LJ_AR)
 
 
+def lj_argon_benchmark(cells: int = 148, seed: int | None = None) -> MDSystem:
+    """The LJ performance test of Sec. 1.7 at its size: a periodic cube, fcc cells^3
+    (148^3 * 4 = 12,967,168 atoms), lattice with small perturbations, 300 steps, the
+    lists rebuilt every 10 steps.  The section gives neither the material nor the
+    temperature, time step or skin; this reading takes the LJ argon of the small
+    system (a = 5.26, eps 0.0104 eV, sigma 3.405, r_c 2.5 sigma), N(0, 0.05^2)
+    displacements, 100 K, dt 2 fs, and a 0.5 angstrom skin, wide enough that no atom
+    moves half of it in ten steps."""
+    pos, box = fcc_lattice(cells, cells, cells, 5.26)
+    x, v = thermal_state(pos, MASS["Ar"], 100.0, 0.05, SEED_BASE + 7 if seed is None else seed)
+    return MDSystem("lj_argon_%d" % (4 * cells ** 3), wrap_into_box(x, box), v, box, MASS["Ar"],
+                    2e-3, 300, 0.5, "lj", lj=LJ_AR, extra={"rebuild_every": 10})
+
+
 def eam_copper(cells: int = 32, seed: int | None = None, K: int = 2000) -> MDSystem:
     """EAM copper: fcc cells^3, a = 3.615, N(0, 0.05^2) displacements, 300 K,
     dt 1 fs, 1000 steps, skin 0.3, 2000-point tables."""

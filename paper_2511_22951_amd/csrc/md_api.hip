@@ -74,6 +74,7 @@ extern "C" int md_plan_count(int n_rep, const md_box* boxes, const int* atom_off
     tiles += (na + tile_atoms - 1) / tile_atoms;
   }
   if (cells > (1LL << 30) || tiles > (1LL << 30)) return MD_ERR_ARG;
+  if (atom_off[n_rep] > MD_MAX_ATOMS) return MD_ERR_ARG;
   *n_cells = (int)cells;
   *n_tiles = (int)tiles;
   return MD_OK;

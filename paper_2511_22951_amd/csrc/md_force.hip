@@ -164,18 +164,21 @@ __device__ __forceinline__ double4 load_rec(const double4* pos, int j) {
                                            (uint32_t)((uint32_t)j << 5));
 }
 
+// List entries are addressed with 32-bit byte offsets when the list holds fewer
+// than 2^30 entries (E = uint32_t), with 64-bit element offsets otherwise.
 __device__ __forceinline__ int load_idx(const int* neigh, uint32_t e) {
   return *reinterpret_cast<const int*>(reinterpret_cast<const char*>(neigh) + (e << 2));
 }
+__device__ __forceinline__ int load_idx(const int* neigh, uint64_t e) { return neigh[e]; }
 
 // Visit the nn list entries of one atom handled by lane l of LANES: entry m sits
 // at element ((m / LANES) * npad + i) * LANES + l, i.e. e0 + (m / LANES) * stride.
 // U entries are in flight per lane: indices first, then records, then the math.
-template <int LANES, int U, typename Load, typename Pair>
-__device__ __forceinline__ void visit_list(const int* neigh, uint32_t e0, uint32_t stride, int l,
-                                           int nn, Load load, Pair pair) {
+template <int LANES, int U, typename E, typename Load, typename Pair>
+__device__ __forceinline__ void visit_list(const int* neigh, E e0, E stride, int l, int nn,
+                                           Load load, Pair pair) {
   int m = l;
-  uint32_t e = e0;
+  E e = e0;
   for (; m + (U - 1) * LANES < nn; m += U * LANES) {
     int j[U];
 #pragma unroll
@@ -196,14 +199,14 @@ __device__ __forceinline__ void visit_list(const int* neigh, uint32_t e0, uint32
 // unconditionally in a fixed order (entries past the lane's end read the atom's
 // first entry and are replaced by the atom itself, `self`), so the compiler can
 // wait for the records alone; pair(q, valid) masks the padding.
-template <int LANES, int U, typename Load, typename Pair>
-__device__ __forceinline__ void visit_list_pipe(const int* neigh, uint32_t e0, uint32_t stride,
-                                                int l, int nn, int self, Load load, Pair pair) {
+template <int LANES, int U, typename E, typename Load, typename Pair>
+__device__ __forceinline__ void visit_list_pipe(const int* neigh, E e0, E stride, int l, int nn,
+                                                int self, Load load, Pair pair) {
   const int cnt = nn > l ? (nn - l + LANES - 1) / LANES : 0;  // this lane's entries
   int jn[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) jn[u] = load_idx(neigh, u < cnt ? e0 + u * stride : e0);
-  uint32_t e = e0 + U * stride;
+  E e = e0 + U * stride;
   for (int b0 = 0; b0 < cnt; b0 += U) {
     decltype(load(0)) q[U];
 #pragma unroll
@@ -315,7 +318,7 @@ __device__ __forceinline__ void step_bookkeeping(md_ctl_dev* ctl) {
 // ---------------------------------------------------------------------------
 // EAM pass 1: rhobar_i = sum_j rho(r_ij), F'(rhobar_i) into pos[i].w, energy.
 // ---------------------------------------------------------------------------
-template <typename R, int LANES, bool EV, bool TLDS, int U>
+template <typename R, int LANES, bool EV, bool TLDS, int U, typename E>
 __device__ __forceinline__ void eam_density_body(
     const md_batch& b, double4* pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const R* __restrict__ rtab_g,
@@ -347,7 +350,7 @@ __device__ __forceinline__ void eam_density_body(
     const double4 pi = load_xyz(pos, i);
     const R rih = (R)g.r_inv_h, rloh = (R)(g.r_lo * g.r_inv_h);
     const float qih = (float)g.q_inv_h, qloh = (float)(g.q_lo * g.q_inv_h);
-    const uint32_t e0 = (uint32_t)i * LANES + S.l, stride = (uint32_t)npad * LANES;
+    const E e0 = (E)i * LANES + S.l, stride = (E)npad * LANES;
     auto run = [&](auto img_tag) {
       constexpr bool IMG = decltype(img_tag)::value;
       auto pair = [&](double4 pj, bool valid) {
@@ -427,14 +430,14 @@ __device__ __forceinline__ void eam_density_body(
   md_batch b, double4 *pos, const int *__restrict__ neigh, const int *__restrict__ nneigh,   \
       int npad, const R *__restrict__ rtab_g, const R *__restrict__ etab, TabGeom g, R rc2,  \
       double *saved, double *partial, long long *ev, int ev_cap, md_ctl_dev *ctl
-template <int LANES, bool EV, bool TLDS>
+template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_density_f32(MD_EAM_DENSITY_ARGS(float)) {
-  eam_density_body<float, LANES, EV, TLDS, 8>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
+  eam_density_body<float, LANES, EV, TLDS, 8, E>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
                                            saved, partial, ev, ev_cap, ctl);
 }
-template <int LANES, bool EV, bool TLDS>
+template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_density_f64(MD_EAM_DENSITY_ARGS(double)) {
-  eam_density_body<double, LANES, EV, TLDS, 4>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
+  eam_density_body<double, LANES, EV, TLDS, 4, E>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
                                             saved, partial, ev, ev_cap, ctl);
 }
 #undef MD_EAM_DENSITY_ARGS
@@ -453,7 +456,7 @@ struct DriftArgs {
   md_walls_dev w;
 };
 
-template <typename R, int LANES, bool EV, bool TLDS>
+template <typename R, int LANES, bool EV, bool TLDS, typename E>
 __device__ __forceinline__ void eam_force_body(
     const md_batch& b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, const TabGeom& g,
@@ -485,7 +488,7 @@ __device__ __forceinline__ void eam_force_body(
     const R fpi = load_fp<R>(pi.w);
     const R rih = (R)g.r_inv_h, rloh = (R)(g.r_lo * g.r_inv_h);
     const float qih = (float)g.q_inv_h, qloh = (float)(g.q_lo * g.q_inv_h);
-    const uint32_t e0 = (uint32_t)i * LANES + S.l, stride = (uint32_t)npad * LANES;
+    const E e0 = (E)i * LANES + S.l, stride = (E)npad * LANES;
     auto run = [&](auto img_tag) {
       constexpr bool IMG = decltype(img_tag)::value;
       auto pair = [&](double4 pj, bool valid) {
@@ -608,43 +611,24 @@ __device__ __forceinline__ void eam_force_body(
       const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, TabGeom g, R rc2, \
       R *force, double *vel, double inv_mass, double half_dt, DriftArgs dr,                     \
       const double *partial, long long *ev, int ev_cap, md_ctl_dev *ctl
-template <int LANES, bool EV, bool TLDS>
+template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_force_f32(
     MD_EAM_FORCE_ARGS(float)) {
-  eam_force_body<float, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
+  eam_force_body<float, LANES, EV, TLDS, E>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
                                          inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);
 }
-template <int LANES, bool EV, bool TLDS>
+template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_force_f64(MD_EAM_FORCE_ARGS(double)) {
-  eam_force_body<double, LANES, EV, TLDS>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
+  eam_force_body<double, LANES, EV, TLDS, E>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
                                           inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);
 }
 #undef MD_EAM_FORCE_ARGS
 
-// One block: per-box sums of the LJ tile partials in fixed order, written as a
-// fixed-point record to ev[(step % ev_cap) * n_rep + rep].
-__global__ __launch_bounds__(1024) void k_ev_reduce(md_batch b, const double* partial,
-                                                    long long* ev, int ev_cap,
-                                                    const md_ctl_dev* ctl) {
-  __shared__ double sh[MD_EV_LEN * 16];
-  const int step = ctl->step;
-  long long* out = ev + (size_t)(step % ev_cap) * b.n_rep * MD_EV_LEN;
-  const int lane = threadIdx.x & (MD_WAVE - 1), wid = threadIdx.x / MD_WAVE;
-  const int nw = blockDim.x / MD_WAVE;
-  for (int r = wid; r < b.n_rep; r += nw) {
-    const int t0 = b.domains[r].tile_off, t1 = t0 + b.domains[r].n_tiles;
-    double v[MD_EV_LEN];
-#pragma unroll
-    for (int k = 0; k < MD_EV_LEN; ++k) v[k] = 0.0;
-    for (int t = t0 + lane; t < t1; t += MD_WAVE)
-#pragma unroll
-      for (int k = 0; k < MD_EV_LEN; ++k) v[k] += partial[(size_t)t * MD_EV_LEN + k];
-#pragma unroll
-    for (int k = 0; k < MD_EV_LEN; ++k) v[k] = md_wave_sum(v[k]);
-    if (lane == 0)
-#pragma unroll
-      for (int k = 0; k < MD_EV_LEN; ++k) out[(size_t)r * MD_EV_LEN + k] = to_fixed(v[k]);
-  }
+// Zero the record slot of the step being evaluated, ahead of the LJ pass whose
+// blocks add into it.
+__global__ __launch_bounds__(64) void k_ev_zero(md_batch b, long long* ev, int ev_cap,
+                                                const md_ctl_dev* ctl) {
+  zero_record(b, ev, ev_cap, ctl->step_next);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,13 +638,14 @@ struct LJc {
   double sig2, eps4, eps24, ucut;
 };
 
-template <typename R, int LANES, bool EV>
+template <typename R, int LANES, bool EV, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_lj(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, LJc c, R rc2, R* force, double* vel,
-    double inv_mass, double half_dt, double* partial, md_ctl_dev* ctl) {
+    double inv_mass, double half_dt, long long* ev, int ev_cap, md_ctl_dev* ctl) {
   constexpr int U = 4;
   __shared__ double sh[MD_EV_LEN * 16];
+  __shared__ double tsum[MD_EV_LEN * 16];
   step_bookkeeping(ctl);
   const Slot S = force_slot<LANES>(b.n_tiles);
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // E, W xx yy zz xy xz yz, K
@@ -681,7 +666,7 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
   if (i >= 0) {
     const Img D(&b.domains[T.rep]);
     const double4 pi = pos[i];
-    const uint32_t e0 = (uint32_t)i * LANES + S.l, stride = (uint32_t)npad * LANES;
+    const E e0 = (E)i * LANES + S.l, stride = (E)npad * LANES;
     auto run = [&](auto img_tag) {
       constexpr bool IMG = decltype(img_tag)::value;
       auto pair = [&](double4 pj) {
@@ -727,13 +712,14 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
     for (int k = 0; k < 6; ++k) acc[1 + k] = 0.5 * (double)w[k];
     double res;
     int gg, kk;
-    if (md_group_waves_sum<8>(acc, LANES, sh, res, gg, kk)) {
-      constexpr int TPB = Shape<LANES>::TPB;
-      const int nlb = (b.n_tiles + TPB - 1) / TPB;
-      const int lb = md_remap_block(nlb);
-      const int t = lb * TPB + gg;
-      if (lb < nlb && t < b.n_tiles) partial[(size_t)t * MD_EV_LEN + kk] = res;
-    }
+    constexpr int TPB = Shape<LANES>::TPB;
+    const int nlb = (b.n_tiles + TPB - 1) / TPB;
+    const int lb = md_remap_block(nlb);
+    if (md_group_waves_sum<8>(acc, LANES, sh, res, gg, kk)) tsum[gg * MD_EV_LEN + kk] = res;
+    __syncthreads();
+    // step_next: block 0 advances ctl->step while the other blocks run
+    accumulate_record<TPB>(b, lb, nlb, tsum,
+                           ev + (size_t)(ctl->step_next % ev_cap) * b.n_rep * MD_EV_LEN);
   }
 }
 
@@ -741,7 +727,8 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
 // host dispatch
 // ---------------------------------------------------------------------------
 bool batch_ok(const md_batch* b) {
-  return b && b->n_rep >= 1 && b->n_atoms >= 0 && b->n_tiles >= 0 && b->n_cells >= 1 &&
+  return b && b->n_rep >= 1 && b->n_atoms >= 0 && b->n_atoms <= MD_MAX_ATOMS &&
+         b->n_tiles >= 0 && b->n_cells >= 1 &&
          b->tile_atoms == MD_TILE && b->domains && (b->tiles || b->n_tiles == 0);
 }
 
@@ -750,6 +737,11 @@ bool nlist_ok(const md_nlist* nl) {
   const int L = nl->lanes;
   if (L != 1 && L != 2 && L != 4 && L != 8 && L != 16) return false;
   return nl->max_neigh >= L && nl->max_neigh % L == 0;
+}
+
+// Lists of 2^30 entries or more (4 GiB) take 64-bit entry offsets in the passes.
+bool md_big_list(const md_nlist& nl, int npad) {
+  return (size_t)nl.max_neigh * (size_t)npad >= ((size_t)1 << 30);
 }
 
 // FP32 tables are staged in LDS when they fit the default dynamic LDS limit
@@ -785,39 +777,46 @@ void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_ta
   const bool ld = table_in_lds<R>(rows, MD_RTAB_W);
   const size_t lds_d = ld ? (size_t)rows * MD_RTAB_W * sizeof(R) : 0;
   const size_t lds_f = ld ? (size_t)rows * MD_FTAB_W * sizeof(R) : 0;
-#define MD_EAM_LAUNCH(EVB, TL_)                                                                 \
+#define MD_EAM_LAUNCH(EVB, TL_, E_)                                                               \
   do {                                                                                         \
     if constexpr (std::is_same<R, float>::value)                                               \
-      MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f32<LANES, EVB, TL_>), grid, block, \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f32<LANES, EVB, TL_, E_>), grid, block, \
                       lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
                       rc2, saved, partial, ev, ev_cap, ctl);                                   \
     else                                                                                       \
-      MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f64<LANES, EVB, TL_>), grid, block, \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f64<LANES, EVB, TL_, E_>), grid, block, \
                       lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
                       rc2, saved, partial, ev, ev_cap, ctl);                                   \
     if constexpr (std::is_same<R, float>::value)                                               \
-      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f32<LANES, EVB, TL_>), grid, block,     \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f32<LANES, EVB, TL_, E_>), grid, block,     \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
                       rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);   \
     else                                                                                       \
-      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f64<LANES, EVB, TL_>), grid, block,     \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f64<LANES, EVB, TL_, E_>), grid, block,     \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
                       rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);   \
   } while (0)
+  const bool big = md_big_list(nl, npad);
+#define MD_EAM_LAUNCH_E(EVB, TL_)                      \
+  do {                                                 \
+    if (big) MD_EAM_LAUNCH(EVB, TL_, uint64_t);        \
+    else MD_EAM_LAUNCH(EVB, TL_, uint32_t);            \
+  } while (0)
   if (ev) {
-    if (ld) MD_EAM_LAUNCH(true, true);
-    else MD_EAM_LAUNCH(true, false);
+    if (ld) MD_EAM_LAUNCH_E(true, true);
+    else MD_EAM_LAUNCH_E(true, false);
   } else {
-    if (ld) MD_EAM_LAUNCH(false, true);
-    else MD_EAM_LAUNCH(false, false);
+    if (ld) MD_EAM_LAUNCH_E(false, true);
+    else MD_EAM_LAUNCH_E(false, false);
   }
+#undef MD_EAM_LAUNCH_E
 #undef MD_EAM_LAUNCH
 }
 
 template <typename R, int LANES>
 void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nlist& nl,
                void* force, double* vel, double inv_mass, double half_dt, long long* ev, int ev_cap,
-               double* partial, md_ctl_dev* ctl, hipStream_t st) {
+               md_ctl_dev* ctl, hipStream_t st) {
   LJc c;
   c.sig2 = p.sigma * p.sigma;
   c.eps4 = 4.0 * p.eps;
@@ -828,16 +827,20 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
   constexpr int TPB = Shape<LANES>::TPB;
   const dim3 grid(md_grid_blocks((b.n_tiles + TPB - 1) / TPB)), block(FBLOCK);
   const int npad = md_npad(b.n_atoms);
+  const bool big = md_big_list(nl, npad);
+#define MD_LJ_LAUNCH(EVB, E_)                                                                  \
+  MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, EVB, E_>), grid, block, 0, st, b,             \
+                  (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,      \
+                  inv_mass, half_dt, ev, ev_cap, ctl)
   if (ev) {
-    MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, true>), grid, block, 0, st, b,
-                    (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,
-                    inv_mass, half_dt, partial, ctl);
-    hipLaunchKernelGGL(k_ev_reduce, dim3(1), dim3(1024), 0, st, b, partial, ev, ev_cap, ctl);
+    hipLaunchKernelGGL(k_ev_zero, dim3(1), dim3(64), 0, st, b, ev, ev_cap, ctl);
+    if (big) MD_LJ_LAUNCH(true, uint64_t);
+    else MD_LJ_LAUNCH(true, uint32_t);
   } else {
-    MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, false>), grid, block, 0, st, b,
-                    (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,
-                    inv_mass, half_dt, partial, ctl);
+    if (big) MD_LJ_LAUNCH(false, uint64_t);
+    else MD_LJ_LAUNCH(false, uint32_t);
   }
+#undef MD_LJ_LAUNCH
 }
 
 }  // namespace
@@ -906,16 +909,14 @@ extern "C" int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec
   if (ev && ev_cap < 1) return MD_ERR_ARG;
   if (vel && !(inv_mass > 0.0)) return MD_ERR_ARG;
   if (b->n_atoms == 0 || b->n_tiles == 0) return MD_OK;
-  const md_ws_layout WL = md_ws_plan(b);
-  double* partial = (double*)((char*)ws + WL.partial);
   hipStream_t st = (hipStream_t)stream;
   md_ctl_dev* c = (md_ctl_dev*)ctl;
   if (prec == MD_FP32) {
     MD_DISPATCH_LANES(nl->lanes, (launch_lj<float, L_>(*b, *p, pos, *nl, force, vel, inv_mass,
-                                                       half_dt, (long long*)ev, ev_cap, partial, c, st)));
+                                                       half_dt, (long long*)ev, ev_cap, c, st)));
   } else {
     MD_DISPATCH_LANES(nl->lanes, (launch_lj<double, L_>(*b, *p, pos, *nl, force, vel, inv_mass,
-                                                        half_dt, (long long*)ev, ev_cap, partial, c, st)));
+                                                        half_dt, (long long*)ev, ev_cap, c, st)));
   }
   MD_LAUNCH_CHECK();
   return MD_OK;

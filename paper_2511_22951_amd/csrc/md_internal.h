@@ -46,8 +46,11 @@ __device__ __forceinline__ bool md_displacement_exceeded(const md_ctl_dev* ctl) 
 
 // Offsets of the workspace regions (bytes, 256-aligned).
 struct md_ws_layout {
-  size_t cell_of, rank, src, sid, counts, pos_s, vel_s, id_s, partial, total;
+  size_t cell_of, rank, src, sid, counts, scan, pos_s, vel_s, id_s, partial, total;
 };
+
+// Blocks of the cell-histogram scan (one segment of cells each).
+#define MD_SCAN_BLOCKS 1024
 
 static inline size_t md_align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -59,6 +62,7 @@ static inline md_ws_layout md_ws_plan(const md_batch* b) {
   L.src = o;     o = md_align256(o + 4 * n);
   L.sid = o;     o = md_align256(o + 4 * n);
   L.counts = o;  o = md_align256(o + 4 * (size_t)(b->n_cells + 1));
+  L.scan = o;    o = md_align256(o + 4 * (size_t)MD_SCAN_BLOCKS);
   L.pos_s = o;   o = md_align256(o + 32 * n);
   L.vel_s = o;   o = md_align256(o + 24 * n);
   L.id_s = o;    o = md_align256(o + 4 * n);

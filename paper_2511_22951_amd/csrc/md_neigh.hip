@@ -106,35 +106,80 @@ _Pragma("unroll")
   if (bad) md_flag(ctl, bad);
 }
 
-// 2. one block: exclusive scan of the histogram into cell_start; counts reset.
-__global__ __launch_bounds__(1024) void k_bin_scan(int n_cells, int mode, int* counts,
+// 2. exclusive scan of the histogram into cell_start (counts reset), over
+// contiguous segments of cells, one 1024-thread block each: segment sums, one
+// block scanning the sums, then each block scanning its segment from its offset.
+__device__ __forceinline__ int block_incl_scan(int v, int* s_w, int& total) {
+  const int lane = threadIdx.x & (MD_WAVE - 1), w = threadIdx.x / MD_WAVE;
+  const int nw = blockDim.x / MD_WAVE;
+#pragma unroll
+  for (int o = 1; o < MD_WAVE; o <<= 1) {
+    const int t = __shfl_up(v, o, MD_WAVE);
+    if (lane >= o) v += t;
+  }
+  if (lane == MD_WAVE - 1) s_w[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int q = 0; q < nw; ++q) {
+      const int t = s_w[q];
+      s_w[q] = run;
+      run += t;
+    }
+    s_w[16] = run;
+  }
+  __syncthreads();
+  v += s_w[w];
+  total = s_w[16];
+  __syncthreads();  // s_w is reused by the next call
+  return v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(int n_cells, int seg, int mode,
+                                                     const int* counts, int* bsum,
+                                                     md_ctl_dev* ctl) {
+  if (skip_rebuild(mode, ctl)) return;
+  __shared__ int s_w[17];
+  const int beg = blockIdx.x * seg, end = min(n_cells, beg + seg);
+  int v = 0;
+  for (int k = beg + threadIdx.x; k < end; k += blockDim.x) v += counts[k];
+  int total;
+  block_incl_scan(v, s_w, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int nb, int n_cells, int mode, int* bsum,
                                                     int* cell_start, md_ctl_dev* ctl) {
   if (skip_rebuild(mode, ctl)) return;
-  __shared__ int part[1024];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int chunk = (n_cells + nt - 1) / nt;
-  const int beg = min(n_cells, tid * chunk), end = min(n_cells, beg + chunk);
-  int sum = 0;
-  for (int k = beg; k < end; ++k) sum += counts[k];
-  part[tid] = sum;
-  __syncthreads();
-  // Hillis-Steele inclusive scan of the chunk sums
-  for (int o = 1; o < nt; o <<= 1) {
-    const int v = tid >= o ? part[tid - o] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int run = part[tid] - sum;
-  for (int k = beg; k < end; ++k) {
-    const int v = counts[k];
-    cell_start[k] = run;
-    run += v;
-    counts[k] = 0;
-  }
-  if (tid == nt - 1) {
-    cell_start[n_cells] = part[nt - 1];
+  __shared__ int s_w[17];
+  const int t = threadIdx.x;
+  const int v = t < nb ? bsum[t] : 0;
+  int total;
+  const int incl = block_incl_scan(v, s_w, total);
+  if (t < nb) bsum[t] = incl - v;
+  if (t == 0) {
+    cell_start[n_cells] = total;
     ctl->n_rebuilds += 1;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(int n_cells, int seg, int mode, int* counts,
+                                                      const int* bsum, int* cell_start,
+                                                      md_ctl_dev* ctl) {
+  if (skip_rebuild(mode, ctl)) return;
+  __shared__ int s_w[17];
+  const int beg = blockIdx.x * seg, end = min(n_cells, beg + seg);
+  int carry = bsum[blockIdx.x];
+  for (int c0 = beg; c0 < end; c0 += blockDim.x) {
+    const int k = c0 + threadIdx.x;
+    const int v = k < end ? counts[k] : 0;
+    int total;
+    const int incl = block_incl_scan(v, s_w, total);
+    if (k < end) {
+      cell_start[k] = carry + incl - v;
+      counts[k] = 0;
+    }
+    carry += total;
   }
 }
 
@@ -447,7 +492,8 @@ __global__ __launch_bounds__(CELL_BLOCK) void k_build(md_batch b, int mode,
 }  // namespace
 
 static bool batch_ok(const md_batch* b) {
-  return b && b->n_rep >= 1 && b->n_atoms >= 0 && b->n_tiles >= 0 && b->n_cells >= 1 &&
+  return b && b->n_rep >= 1 && b->n_atoms >= 0 && b->n_atoms <= MD_MAX_ATOMS &&
+         b->n_tiles >= 0 && b->n_cells >= 1 &&
          b->tile_atoms == MD_TILE && b->domains && (b->tiles || b->n_tiles == 0);
 }
 
@@ -474,8 +520,17 @@ extern "C" int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos
   MD_LAUNCH_TIMED(MD_KERNEL_BIN_COUNT, k_bin_count, grid, block, 0, st, *b, (int)mode,
                   (double4*)pos, cell_of, rank_of, counts, c);
   MD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, b->n_cells, (int)mode, counts,
+  const int nb = std::min(MD_SCAN_BLOCKS, (b->n_cells + 1023) / 1024);
+  const int seg = (b->n_cells + nb - 1) / nb;
+  int* bsum = (int*)(w + L.scan);
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(1024), 0, st, b->n_cells, seg, (int)mode,
+                     counts, bsum, c);
+  MD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, nb, b->n_cells, (int)mode, bsum,
                      cell_start, c);
+  MD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, b->n_cells, seg, (int)mode,
+                     counts, bsum, cell_start, c);
   MD_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_bin_scatter, grid, block, 0, st, *b, (int)mode, cell_of, rank_of,
                      cell_start, id, src, sid, c);

@@ -84,3 +84,32 @@ def test_al640k_shock_configuration():
                              rng.choice(n, 128, replace=False)])
     _check_forces(sim, s, sample, 1e-5, 1e-4)
     _check_sets(sim, s, sample)
+
+
+def test_lj13m_paper_configuration():
+    """The LJ test of Sec. 1.7 at its size: 12,967,168 Ar atoms, lists rebuilt every 10
+    steps (the list holds over 2^30 entries, so the passes take 64-bit entry offsets);
+    FP64 and FP32-mixed, 20 steps with 10-step graphs."""
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.lj_argon_benchmark()
+    n = s.pos.shape[0]
+    sample = np.random.default_rng(2026).choice(n, 128, replace=False)
+    for prec, tol, tol_net in ((N.MD_FP64, 1e-11, 1e-10), (N.MD_FP32, 1e-5, 1e-5)):
+        sim = Simulation(s, precision=prec, lanes=2, max_neigh=112, ev_cap=64,
+                         rebuild_every=10).setup()
+        assert sim.nl.max_neigh * sim.nl.npad >= 1 << 30
+        n0 = sim.state.check_flags()["n_rebuilds"]
+        sim.run(20, graph_steps=10)
+        assert sim.state.check_flags()["n_rebuilds"] - n0 == 2
+        x = sim.state.positions()
+        f = sim.state.forces()
+        lj = s.lj
+        r = core.lj_sampled(x, s.box, lj.eps, lj.sigma, lj.r_cut, sample)
+        err = np.linalg.norm(f[sample] - r.force) / np.linalg.norm(r.force)
+        assert err < tol, (prec, err)
+        net = np.abs(f.sum(axis=0)).max() / np.abs(f).sum()
+        assert net < tol_net, (prec, net)
+        if prec == N.MD_FP64:
+            _check_sets(sim, s, sample)
+        del sim
