@@ -48,11 +48,12 @@ def parse():
                     help="only copy MIB MiB device to device a few times (the known-size "
                          "transfer that scales the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--workload", choices=["cu131k", "al_shock", "cold_curve", "force_matching",
-                                           "lj13m"],
+                                           "lj13m", "nvt"],
                     default="cu131k",
                     help="cu131k: the headline EAM Cu NVE run; the others are the secondary "
                          "measurements (640k-atom Al shock, 64 batched cold-curve replicas, "
-                         "force-matching epochs, the 13M-atom LJ test of Sec. 1.7)")
+                         "force-matching epochs, the 13M-atom LJ test of Sec. 1.7, Cu with a "
+                         "Langevin thermostat)")
     ap.add_argument("--unfused", action="store_true",
                     help="run the kick-drift as its own pass instead of fusing it into the force "
                          "pass")
@@ -253,7 +254,8 @@ def main():
         args.steps = 1000
     if args.workload != "cu131k":
         {"al_shock": bench_al_shock, "cold_curve": bench_cold_curve,
-         "force_matching": bench_force_matching, "lj13m": bench_lj_paper}[args.workload](args)
+         "force_matching": bench_force_matching, "lj13m": bench_lj_paper,
+         "nvt": bench_nvt}[args.workload](args)
         return
     import torch
     import mdinputs as mi
@@ -507,6 +509,64 @@ def bench_lj_paper(args):
             "cores": core.num_threads(), "kind": "oracle",
             "sample": "FP64 O(N) force sums of %d sampled atoms over all %d atoms, %.1f s"
                       % (len(sample), n, dt)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_nvt(args):
+    """EAM Cu 131,072 atoms, FP32-mixed forces, NVT: the Langevin update of the whole box
+    (300 K, stiffness 0.5/ps as in Secs. 3.2-3.3) in the kick-drift kernel, lists rebuilt
+    every 9 steps; beside the same run without the thermostat (kick-drift unfused in both)."""
+    import torch
+    import mdinputs as mi
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    N.lib()
+    system = mi.eam_copper(cells=32)
+    n = system.pos.shape[0]
+    steps = args.steps or 1000
+    k = args.rebuild_every if args.rebuild_every > 0 else 9
+    gs = max(2 * k, args.graph_steps // k * k)
+    lanes = args.lanes or autotune_lanes(system, N.MD_FP32)
+    lang = {"seed": 2511, "regions": [{"T": 300.0, "gamma": 0.5}]}
+    res = {}
+    for name, thermo in (("nvt", lang), ("nve", None)):
+        cap = args.warmup + steps + args.kernel_samples + 8
+        sim = Simulation(system, precision=N.MD_FP32, lanes=lanes, ev_cap=cap, rebuild_every=k,
+                         thermostat=thermo).setup()
+        sim.run(args.warmup, graph_steps=gs)
+        torch.cuda.synchronize()
+        st0 = sim.state.read_flags()[1]
+        ms = _gpu_time(lambda: sim.run(steps, graph_steps=gs), 1)
+        status, info = sim.state.read_flags()
+        N.check(status, "device flags after the timed run")
+        ev = sim.energies(range(info["step"] - steps + 1, info["step"] + 1))
+        temps = 2.0 * ev[:, 7] / ((3 * n - 3) * 8.617333262e-5)
+        kd = time_kernel(N, "kick_drift", lambda: sim.step(), args.kernel_samples)[0]
+        res[name] = {"atom_steps_per_s": n * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                     "kick_drift_us": 1e3 * kd, "mean_T_K": float(temps.mean()),
+                     "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"]}
+        del sim
+    # kick-drift traffic per atom: read v 24, f 12, x 32, x_ref 24 (and id 4 with the
+    # thermostat); write v 24, x 32
+    kd_bytes = n * (148.0 + 4.0)
+    achieved = kd_bytes / (res["nvt"]["kick_drift_us"] * 1e-6) / 1e9
+    out = {
+        "metric": "atom-steps/s (EAM Cu NVT, Langevin thermostat)",
+        "value": res["nvt"]["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": res["nvt"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "EAM Cu fcc 32^3 = 131072 atoms, 300 K, dt 1 fs, skin 0.3, "
+                               "Langevin 300 K / 0.5 per ps over the whole box, rebuild every "
+                               "%d steps" % k, "n_atoms": n, "lanes_per_atom": lanes,
+                   "graph_steps": gs},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_kick_drift (Langevin)",
+                     "kernel_us": res["nvt"]["kick_drift_us"], "bytes_per_launch": kd_bytes},
+        "paths": res,
+        "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

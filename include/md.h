@@ -160,6 +160,41 @@ typedef struct md_walls {
   double top;
 } md_walls;
 
+/* Langevin thermostat (Sec. 1.5: a Langevin force added to eq. 1.5 gives the NVT
+ * ensemble; Sec. 3.1 thermostats slabs of the sample, each with a target
+ * temperature, a mean velocity and a stiffness).  In each region the equation of
+ * motion gains -m gamma (v - u) + sqrt(2 m gamma k_B T) eta(t).  Discretisation:
+ * the exact Ornstein-Uhlenbeck velocity update over dt, applied at the start of
+ * md_verlet_step(MD_KICK_DRIFT) before the half kick (the OBABO splitting of
+ * Bussi and Parrinello, Phys. Rev. E 75, 056707 (2007), with its two half-step
+ * O parts merged):
+ *   v <- u + c1 (v - u) + c2 xi,  c1 = exp(-gamma dt),  c2 = sqrt((1 - c1^2) k_B T / m).
+ * xi holds three standard normals per atom and step from Philox4x32-10 (Salmon,
+ * Moraes, Dror and Shaw, SC'11) with counter {id, step, 0, 0} and key {seed low
+ * 32 bits, seed high 32 bits}, by the Box-Muller transform of its four words
+ * w0..w3: with U_k = (w_k + 1) 2^-32 for k = 0, 2 and U_k = w_k 2^-32 for
+ * k = 1, 3, xi_x = sqrt(-2 ln U_0) cos(2 pi U_1), xi_y = sqrt(-2 ln U_0)
+ * sin(2 pi U_1), xi_z = sqrt(-2 ln U_2) cos(2 pi U_3).  step is the number of the
+ * step being started (the control block's step + 1), id the atom's original id,
+ * so the noise does not depend on the cell order.  An atom belongs to the first
+ * region with lo <= x[axis] < hi, x at the start of the step and, on a periodic
+ * axis, folded into the box as md_bin_cells wraps it; atoms outside every region
+ * follow plain velocity Verlet. */
+#define MD_MAX_THERMO_REGIONS 4
+typedef struct md_thermo_region {
+  double lo, hi;       /* slab along md_langevin.axis, angstrom (+-HUGE_VAL: unbounded) */
+  double temperature;  /* K, >= 0 */
+  double gamma;        /* friction (stiffness), 1/ps, >= 0 */
+  double u[3];         /* mean velocity, angstrom/ps */
+} md_thermo_region;
+typedef struct md_langevin {
+  const int* id;       /* device [n]: original atom ids (md_bin_cells keeps them in step) */
+  unsigned long long seed;
+  int axis;            /* 0, 1 or 2 */
+  int n_regions;       /* 1 .. MD_MAX_THERMO_REGIONS */
+  md_thermo_region region[MD_MAX_THERMO_REGIONS];
+} md_langevin;
+
 /* Per-step thermodynamic record per box: {E_pot, W_xx, W_yy, W_zz, W_xy, W_xz,
  * W_yz, K}, W the pair virial 1/2 sum_ij r_ij f_ij (Appendix), K the kinetic
  * energy (eq. 1.3).  Stored as signed 64-bit fixed point, MD_EV_SCALE units per
@@ -280,14 +315,17 @@ int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec, const v
                   long long* ev, int ev_cap, void* ws,
                   void* ctl, void* stream);
 
-/* Velocity Verlet (Sec. 1.5).  MD_KICK_DRIFT: v += half_dt f/m; x += dt v; walls
- * at t = (step + 1) dt; per-block maxima of |x - pos_ref|^2 are kept for the
- * rebuild decision (compared with half_skin^2; half_skin < 0: no criterion).  The
- * step counter advances in the next force pass.  MD_KICK: v += half_dt f/m only. */
+/* Velocity Verlet (Sec. 1.5).  MD_KICK_DRIFT: the Langevin update if lang is not
+ * NULL (md_langevin), then v += half_dt f/m; x += dt v; walls at t = (step + 1) dt;
+ * per-block maxima of |x - pos_ref|^2 are kept for the rebuild decision (compared
+ * with half_skin^2; half_skin < 0: no criterion).  The step counter advances in
+ * the next force pass.  MD_KICK: v += half_dt f/m only (lang must be NULL).
+ * MD_ERR_ARG for a malformed md_langevin (region count, axis, negative T or
+ * gamma, NULL id). */
 int md_verlet_step(const md_batch* b, md_verlet_phase phase, double dt, double* pos,
                    double* vel, const void* force, md_precision prec, double inv_mass,
-                   const md_walls* walls, const double* pos_ref, double half_skin, void* ctl,
-                   void* stream);
+                   const md_walls* walls, const md_langevin* lang, const double* pos_ref,
+                   double half_skin, void* ctl, void* stream);
 
 /* Vector-Jacobian product of the EAM forces with respect to the three spline
  * coefficient vectors: grad_coef[phi | rho | F] += sum_i G_i . dF_i/dc for a

@@ -16,6 +16,7 @@ MD_EV_SCALE = 2.0 ** 36  # fixed-point units per eV of the per-box records
 MD_TILE = 64
 MD_NN_IMG = 1 << 30
 FLAG_NEIGH_OVERFLOW, FLAG_TABLE_RANGE, FLAG_WALL, FLAG_NONFINITE, FLAG_STALE_LIST = 1, 2, 4, 8, 16
+MD_ERR_ARG = -1
 MD_ERR_STALE_LIST = -9
 
 
@@ -70,6 +71,19 @@ class Walls(C.Structure):
                 ("piston_v", C.c_double), ("top", C.c_double)]
 
 
+MD_MAX_THERMO_REGIONS = 4
+
+
+class ThermoRegion(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("temperature", C.c_double),
+                ("gamma", C.c_double), ("u", C.c_double * 3)]
+
+
+class Langevin(C.Structure):
+    _fields_ = [("id", C.c_void_p), ("seed", C.c_ulonglong), ("axis", C.c_int),
+                ("n_regions", C.c_int), ("region", ThermoRegion * MD_MAX_THERMO_REGIONS)]
+
+
 class Drift(C.Structure):
     _fields_ = [("pos_out", C.c_void_p), ("pos_ref", C.c_void_p), ("dt", C.c_double),
                 ("half_skin", C.c_double), ("walls", Walls)]
@@ -94,8 +108,8 @@ _SIGS = {
                           _vp, _vp]),
     "md_eam_forces": (_i, [_P(Batch), _P(EAM), _i, _vp, _vp, _P(NList), _vp, _vp, _vp, _d, _d,
                            _P(Drift), _vp, _i, _vp, _vp, _vp]),
-    "md_verlet_step": (_i, [_P(Batch), _i, _d, _vp, _vp, _vp, _i, _d, _P(Walls), _vp, _d, _vp,
-                            _vp]),
+    "md_verlet_step": (_i, [_P(Batch), _i, _d, _vp, _vp, _vp, _i, _d, _P(Walls), _P(Langevin),
+                            _vp, _d, _vp, _vp]),
     "md_eam_backward": (_i, [_P(Batch), _P(EAM), _i, _vp, _P(NList), _vp, _vp, _vp, _vp, _vp,
                              _vp]),
     "md_backward_workspace_bytes": (_sz, [_P(Batch), _P(EAM)]),

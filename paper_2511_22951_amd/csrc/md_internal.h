@@ -124,6 +124,74 @@ static inline int md_walls_load(const md_walls* walls, md_walls_dev* w) {
   return MD_OK;
 }
 
+// Langevin thermostat in device form: per region the slab bounds, the decay
+// c1 = exp(-gamma dt), the noise amplitude c2 = sqrt((1 - c1^2) k_B T / m) in
+// angstrom/ps and the mean velocity.
+struct md_langevin_dev {
+  const int* id;
+  unsigned key0, key1;
+  int axis, n;
+  double lo[MD_MAX_THERMO_REGIONS], hi[MD_MAX_THERMO_REGIONS];
+  double c1[MD_MAX_THERMO_REGIONS], c2[MD_MAX_THERMO_REGIONS];
+  double u[MD_MAX_THERMO_REGIONS][3];
+};
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32 -> 64-bit
+// multiplies with the Weyl key schedule.
+__device__ __forceinline__ void md_philox4x32_10(unsigned (&c)[4], unsigned k0, unsigned k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const unsigned a = c[0], b = c[2];
+    const unsigned hi0 = __umulhi(0xD2511F53u, a), lo0 = 0xD2511F53u * a;
+    const unsigned hi1 = __umulhi(0xCD9E8D57u, b), lo1 = 0xCD9E8D57u * b;
+    c[0] = hi1 ^ c[1] ^ k0;
+    c[1] = lo1;
+    c[2] = hi0 ^ c[3] ^ k1;
+    c[3] = lo0;
+  }
+}
+
+// Three standard normals for (id, step): Box-Muller on the four Philox words.
+__device__ __forceinline__ void md_langevin_normals(int id, int step, unsigned k0, unsigned k1,
+                                                    double (&z)[3]) {
+  unsigned c[4] = {(unsigned)id, (unsigned)step, 0u, 0u};
+  md_philox4x32_10(c, k0, k1);
+  const double s32 = 2.3283064365386963e-10;  // 2^-32
+  const double two_pi = 6.283185307179586;
+  const double u0 = ((double)c[0] + 1.0) * s32, u1 = (double)c[1] * s32;
+  const double u2 = ((double)c[2] + 1.0) * s32, u3 = (double)c[3] * s32;
+  const double r0 = sqrt(-2.0 * log(u0)), r2 = sqrt(-2.0 * log(u2));
+  z[0] = r0 * cos(two_pi * u1);
+  z[1] = r0 * sin(two_pi * u1);
+  z[2] = r2 * cos(two_pi * u3);
+}
+
+// The Langevin velocity update of one atom at position x (start of the step); the
+// region coordinate is folded into the box on a periodic axis, as the wrap of the
+// binning pass does (x - L floor((x - lo) / L), lo + L going to lo).
+__device__ __forceinline__ void md_langevin_atom(const md_langevin_dev& L, const md_domain& D,
+                                                 int i, int step, const double (&x)[3],
+                                                 double (&v)[3]) {
+  const int a = L.axis;
+  double xa = a == 0 ? x[0] : (a == 1 ? x[1] : x[2]);
+  if (D.periodic[a]) {
+    xa = xa - D.len[a] * floor((xa - D.lo[a]) / D.len[a]);
+    if (xa >= D.lo[a] + D.len[a]) xa = D.lo[a];
+  }
+  int r = -1;
+  for (int q = L.n - 1; q >= 0; --q)
+    if (xa >= L.lo[q] && xa < L.hi[q]) r = q;
+  if (r < 0) return;
+  double z[3];
+  md_langevin_normals(L.id[i], step, L.key0, L.key1, z);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = L.u[r][k] + L.c1[r] * (v[k] - L.u[r][k]) + L.c2[r] * z[k];
+}
+
 // The drift of velocity Verlet for one atom: x <- x + dt v (x holds the old
 // position on entry), then the walls at t_new: a piston plane z0 + v_p t that
 // reflects specularly in its own frame, and a static top wall (Sec. 1.5).  Shared

@@ -297,11 +297,38 @@ def md_eam_forces(st: State, pot: EAMPotential, nl: NeighborList, table=None, sa
           "md_eam_forces")
 
 
-def md_verlet_step(st: State, phase, dt, inv_mass, walls=None, half_skin=-1.0, stream=None):
+def langevin_params(st: State, thermostat):
+    """md_langevin from {"seed": int, "axis": 0-2, "regions": [{"lo", "hi", "T", "gamma",
+    "u": (ux, uy, uz)}, ...]} (lo/hi default to an unbounded slab, u to zero)."""
+    if thermostat is None or isinstance(thermostat, N.Langevin):
+        return thermostat
+    regs = thermostat["regions"]
+    if not 1 <= len(regs) <= N.MD_MAX_THERMO_REGIONS:
+        raise ValueError("1 to %d thermostat regions" % N.MD_MAX_THERMO_REGIONS)
+    lg = N.Langevin()
+    lg.id = _ptr(st.id)
+    lg.seed = int(thermostat.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    lg.axis = int(thermostat.get("axis", 2))
+    lg.n_regions = len(regs)
+    for q, r in enumerate(regs):
+        g = lg.region[q]
+        g.lo = float(r.get("lo", -math.inf))
+        g.hi = float(r.get("hi", math.inf))
+        g.temperature = float(r["T"])
+        g.gamma = float(r["gamma"])
+        for k, x in enumerate(r.get("u", (0.0, 0.0, 0.0))):
+            g.u[k] = float(x)
+    return lg
+
+
+def md_verlet_step(st: State, phase, dt, inv_mass, walls=None, half_skin=-1.0, langevin=None,
+                   stream=None):
     w = walls_params(walls) if isinstance(walls, dict) else walls
+    lg = langevin_params(st, langevin)
     check(N.lib().md_verlet_step(C.byref(st.plan.c), phase, float(dt), _ptr(st.pos), _ptr(st.vel),
                                  _ptr(st.force), st.precision, float(inv_mass),
-                                 C.byref(w) if w is not None else None, _ptr(st.pos_ref),
+                                 C.byref(w) if w is not None else None,
+                                 C.byref(lg) if lg is not None else None, _ptr(st.pos_ref),
                                  float(half_skin), _ptr(st.ctl), _stream(stream)),
           "md_verlet_step")
 

@@ -14,6 +14,10 @@ The arithmetic is the same, bit for bit; between steps the state is then one
 kick-drift ahead: positions x(n + 1), velocities v(n + 1/2) (`previous_positions`
 returns x(n)).
 
+With a thermostat ({"seed", "axis", "regions": [{"lo", "hi", "T", "gamma", "u"}]}) the
+kick-drift starts with the Langevin velocity update of md_langevin (NVT, Sec. 1.5);
+the kick-drift is then never fused.
+
 Rebuild policies (both in the paper):
   rebuild_every = 0: on the threshold (Sec. 1.4) -- the rebuild kernels run every
       step in MD_IF_FLAGGED mode and do work only when an atom moved > skin/2;
@@ -35,9 +39,10 @@ from . import md
 
 class Simulation:
     def __init__(self, system, precision=N.MD_FP64, lanes=4, max_neigh=128, ev_cap=1024,
-                 device="cuda", table=None, rebuild_every=0, fused=False):
+                 device="cuda", table=None, rebuild_every=0, fused=False, thermostat=None):
         self.sys = system
-        self.fused = bool(fused) and system.potential != "lj"
+        # the Langevin update runs in the kick-drift kernel, so it is not fused
+        self.fused = bool(fused) and system.potential != "lj" and thermostat is None
         self.primed = False  # fused: the last force pass already did the next kick-drift
         self.pos_alt = None
         self.rebuild_every = int(rebuild_every)
@@ -52,6 +57,7 @@ class Simulation:
         self.dt = system.dt_ps
         self.half_skin = 0.5 * system.skin
         self.walls = md.walls_params(system.walls)
+        self.langevin = md.langevin_params(self.state, thermostat)
         self.ev_cap = ev_cap
         self.ev = md.ev_buffer(ev_cap, 1, device)
         if system.potential == "lj":
@@ -99,7 +105,7 @@ class Simulation:
         st = self.state
         if not self.primed:
             md.md_verlet_step(st, N.MD_KICK_DRIFT, self.dt, self.inv_mass, self.walls,
-                              self.half_skin)
+                              self.half_skin, langevin=self.langevin)
         k = self.rebuild_every
         if k <= 0:
             md.md_bin_cells(st, N.MD_IF_FLAGGED)

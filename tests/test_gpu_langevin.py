@@ -1,0 +1,129 @@
+"""GPU parity of the Langevin thermostat (md_langevin in md_verlet_step) with the
+oracle (oracle/thermostat.py), through the C ABI.
+
+  device normals          Philox4x32-10 + Box-Muller per (seed, step, id), regions   1e-13
+  NVT trajectories        LJ Ar 256 / EAM Cu 256 atoms, two slabs and a free zone,
+                          40 steps with a 20-step graph: positions / velocities       1e-9 / 1e-8
+                          (FP64), 1e-6 / 1e-4 (FP32-mixed forces)
+  thermalisation          EAM Cu 4000 atoms, 300 K -> 600 K, mean T of the last
+                          1000 steps within 3 %
+  argument checks         malformed md_langevin -> MD_ERR_ARG
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import mdinputs as mi
+from oracle import integrate, thermostat as th
+
+pytestmark = pytest.mark.gpu
+
+
+def _lang(seed=99, axis=1, gamma=5.0):
+    return {"seed": seed, "axis": axis, "regions": [
+        {"lo": 0.0, "hi": 7.0, "T": 300.0, "gamma": gamma, "u": (0.0, 0.0, 1.0)},
+        {"lo": 7.0, "hi": 14.0, "T": 50.0, "gamma": gamma, "u": (0.5, 0.0, 0.0)}]}
+
+
+def test_device_normals_match_oracle():
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd import md
+    n, L, mass, dt = 5000, 21.0, 39.948, 2e-3
+    rng = np.random.default_rng(17)
+    x = rng.uniform(0.0, L, (n, 3))
+    v = rng.normal(0.0, 2.0, (n, 3))
+    box = mi.Box((0.0, 0.0, 0.0), (L, L, L), (1, 1, 1))
+    ids = rng.permutation(n).astype(np.int32)  # noise is keyed by id, not by slot
+    plan = md.Plan([box], [n], 5.0)
+    st = md.State(plan, x, v, N.MD_FP64, ids=ids)
+    lang = _lang(seed=(7 << 32) + 12345, gamma=1e7)  # exp(-gamma dt) = 0: v = u + c2 xi
+    md.md_verlet_step(st, N.MD_KICK_DRIFT, dt, 1.0 / mass, langevin=lang)
+    got = st.vel.t().cpu().numpy()
+    want = th.o_step(x, v, ids, 1, lang, mass, dt)  # step 1: the first step
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13)
+    free = x[:, 1] >= 14.0
+    assert free.any() and np.array_equal(got[free], v[free])
+    # the next step draws new numbers
+    md.md_verlet_step(st, N.MD_KICK_DRIFT, dt, 1.0 / mass, langevin=lang)
+    got2 = st.vel.t().cpu().numpy()
+    assert not np.allclose(got2[~free], got[~free])
+
+
+def _run_pair(system, prec, lanes, steps=40, graph=20):
+    from paper_2511_22951_amd.sim import Simulation
+    lang = _lang()
+    sim = Simulation(system, precision=prec, lanes=lanes, ev_cap=64, thermostat=lang).setup()
+    sim.run(steps, graph_steps=graph)
+    sim.state.check_flags()
+    n = system.pos.shape[0]
+    if system.potential == "lj":
+        fn = integrate.lj_force_fn(system.box, system.lj)
+    else:
+        from oracle import core
+        fn = integrate.eam_force_fn(system.box, core.EAMPotential.from_table(system.table))
+    xo, vo, _, _ = th.run_nvt(system.pos, system.vel, np.arange(n), system.box, system.mass,
+                              system.dt_ps, steps, fn, lang)
+    return sim.state.positions(), sim.state.velocities(), xo, vo, system.box
+
+
+def _min_image(d, box):
+    ln = np.asarray(box.len)
+    return d - ln * np.rint(d / ln)
+
+
+@pytest.mark.parametrize("case", ["lj_fp64", "eam_fp64", "eam_fp32"])
+def test_nvt_trajectory_matches_oracle(case):
+    from paper_2511_22951_amd import _native as N
+    if case == "lj_fp64":
+        s, prec, tol_x, tol_v = mi.lj_argon(cells=4), N.MD_FP64, 1e-9, 1e-8
+    else:
+        s = mi.eam_copper(cells=4)
+        prec = N.MD_FP64 if case == "eam_fp64" else N.MD_FP32
+        tol_x, tol_v = (1e-9, 1e-8) if prec == N.MD_FP64 else (1e-6, 1e-4)
+    xg, vg, xo, vo, box = _run_pair(s, prec, 4)
+    assert np.abs(_min_image(xg - xo, box)).max() < tol_x
+    assert np.abs(vg - vo).max() < tol_v
+
+
+def test_nvt_reaches_target_temperature():
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.eam_copper(cells=10)
+    n = s.pos.shape[0]
+    lang = {"seed": 5, "regions": [{"T": 600.0, "gamma": 10.0}]}
+    sim = Simulation(s, precision=N.MD_FP32, lanes=2, ev_cap=2048, thermostat=lang).setup()
+    sim.run(1500, graph_steps=50)
+    sim.state.check_flags()
+    ev = sim.energies(range(501, 1501))
+    temps = 2.0 * ev[:, 7] / ((3 * n - 3) * th.KB)
+    assert abs(temps.mean() / 600.0 - 1.0) < 0.03, temps.mean()
+
+
+def test_malformed_thermostat_is_rejected():
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd import md
+    s = mi.lj_argon(cells=2)
+    plan = md.Plan([s.box], [s.pos.shape[0]], 4.0)
+    st = md.State(plan, s.pos, s.vel, N.MD_FP64)
+    good = {"seed": 1, "regions": [{"T": 10.0, "gamma": 1.0}]}
+    md.md_verlet_step(st, N.MD_KICK_DRIFT, 1e-3, 1.0 / s.mass, langevin=good)
+    bad = [md.langevin_params(st, good) for _ in range(5)]
+    bad[0].n_regions = 0
+    bad[1].axis = 3
+    bad[2].region[0].temperature = -1.0
+    bad[3].region[0].gamma = float("nan")
+    bad[4].id = None
+    L = N.lib()
+    for lg in bad:
+        rc = L.md_verlet_step(C.byref(plan.c), N.MD_KICK_DRIFT, 1e-3, md._ptr(st.pos),
+                              md._ptr(st.vel), md._ptr(st.force), N.MD_FP64, 1.0 / s.mass, None,
+                              C.byref(lg), md._ptr(st.pos_ref), -1.0, md._ptr(st.ctl),
+                              md._stream())
+        assert rc == N.MD_ERR_ARG
+    # MD_KICK takes no thermostat
+    rc = L.md_verlet_step(C.byref(plan.c), N.MD_KICK, 1e-3, md._ptr(st.pos), md._ptr(st.vel),
+                          md._ptr(st.force), N.MD_FP64, 1.0 / s.mass, None,
+                          C.byref(md.langevin_params(st, good)), md._ptr(st.pos_ref), -1.0,
+                          md._ptr(st.ctl), md._stream())
+    assert rc == N.MD_ERR_ARG
