@@ -401,6 +401,16 @@ def bench_al_shock(args):
         kt[kname] = time_kernel(N, kname, lambda: sim.step(), args.kernel_samples)[0]
     nn = sim.nl.lengths().double()
     zc = sim.state.positions()[:, 2]
+    # analysis path (Appendix): per-atom energy and virial, then 257 slab profiles along z
+    from paper_2511_22951_amd import md
+    obs = {}
+    obs_ms = _gpu_time(lambda: obs.update(
+        zip("ewr", md.md_atom_observables(sim.state, sim.nl, eam=sim.pot))), 5) / 5
+    lz, nb = system.box.len[2] + 1.0, 257
+    pws = torch.empty(int(N.lib().md_profile_workspace_bytes(nb)), dtype=torch.uint8,
+                      device="cuda")
+    prof_ms = _gpu_time(lambda: md.md_profiles(sim.state, 2, 0.0, lz / nb, nb, system.mass,
+                                               obs["e"], obs["w"], ws=pws), 5) / 5
     rebuild_ms = _gpu_time(lambda: sim.rebuild(), 5) / 5
     kt_force = kt["eam_force"] * 1e-3
     bytes_force = algorithmic_force_bytes(n, nn.mean().item(), 4, fused=sim.fused)
@@ -424,6 +434,8 @@ def bench_al_shock(args):
         "atoms_min_z": float(zc.min()),
         "kernel_us": {k: 1e3 * v for k, v in kt.items()},
         "rebuild_us": 1e3 * rebuild_ms,
+        "analysis_us": {"atom_observables_fp64": 1e3 * obs_ms,
+                        "profiles_257_slabs": 1e3 * prof_ms},
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

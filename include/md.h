@@ -339,6 +339,45 @@ int md_eam_backward(const md_batch* b, const md_eam* p, md_precision prec, const
                     const md_nlist* nl, const double* saved, const double* grad_force,
                     double* grad_coef, void* ws, void* ctl, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Analysis (Appendix)
+ * ------------------------------------------------------------------------- */
+
+/* Per-atom potential energy and pair virial in FP64 from the current list (valid
+ * as for the force passes), for exactly one of eam / lj:
+ *   EAM: e_i = F(rhobar_i) + 1/2 sum_j phi(r_ij), evaluated from the B-spline
+ *        coefficients; rho_fp[2][n] receives {rhobar_i, F'(rhobar_i)} (required);
+ *   LJ:  e_i = 1/2 sum_j U(r_ij) (shifted as in md_lj_forces); rho_fp unused.
+ *   w_atom[6][n] = 1/2 sum_j r_ij (x) f_ij (order xx yy zz xy xz yz), r_ij = x_i - x_j,
+ *   f_ij the central pair force on i due to j (the Appendix virial read with the pair
+ *   force), so sum_i e_i and sum_i w_i are the totals of the force passes' records.
+ * Output arrays are [n] / [6][n] FP64 in the current atom order.  Sets
+ * MD_FLAG_TABLE_RANGE like the force passes. */
+int md_atom_observables(const md_batch* b, const md_eam* eam, const md_lj* lj, const double* pos,
+                        const md_nlist* nl, double* e_atom, double* w_atom, double* rho_fp,
+                        void* ctl, void* stream);
+
+/* Profiles over n_bins slabs [lo + l width, lo + (l + 1) width) along `axis` of a
+ * single box (n_rep = 1; on a periodic axis x is folded into the box first), the
+ * statistical definitions of the Appendix for atoms of equal mass (u):
+ *   N_l, M_l = N_l m, u_l = sum v / N_l (centre-of-mass velocity),
+ *   K_l = sum m (v - u_l) (x) (v - u_l) (eV), T^a_l = K^aa_l / (k_B N_l), T_l = mean,
+ *   P_l = (K_l + W_l) / V_l (eV/A^3) with W_l = sum of w_atom over the slab and V_l =
+ *   width times the box cross-section, P = trace / 3,
+ *   E_pot / M_l = sum e / M_l and E_int / M_l = (sum e + tr K / 2) / M_l (eV/u).
+ * out[n_bins][MD_PROF_LEN] (device FP64): N, M, u[3], T^x, T^y, T^z, T,
+ * P^{xx yy zz xy xz yz}, P, E_pot/M, E_int/M; empty slabs give zeros.  e_atom and
+ * w_atom (md_atom_observables) may be NULL, which zeroes their terms.  Slab sums are
+ * accumulated as 64-bit fixed point (2^32 units per eV, angstrom/ps or atom), so the
+ * result is reproducible bit for bit; each slab sum must stay within +-2^31 of its
+ * unit.  ws: md_profile_workspace_bytes(n_bins) bytes. */
+#define MD_PROF_LEN 18
+#define MD_MAX_PROFILE_BINS 65536
+size_t md_profile_workspace_bytes(int n_bins);
+int md_profiles(const md_batch* b, int axis, double lo, double width, int n_bins,
+                const double* pos, const double* vel, double mass, const double* e_atom,
+                const double* w_atom, double* out, void* ws, void* stream);
+
 /* Copy the control block's sticky flags and counters to host memory
  * host_out[4] = {flags, step, n_rebuilds, max_nneigh} and synchronise the
  * stream.  Returns the md_status of the most severe flag set (MD_OK if none). */

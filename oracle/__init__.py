@@ -13,10 +13,12 @@ Contents (each function cites the passage it follows):
   integrate  velocity Verlet (kick-drift-kick) with the piston and top walls.
   thermostat Langevin velocity update per slab region (NVT), with the Philox4x32-10
              counter-based generator and Box-Muller normals it draws from.
+  profiles   slab profiles of the Appendix (centre-of-mass velocity, temperature
+             per axis, pressure tensor, potential and internal energy per mass).
   adjoint    force-matching loss and its exact gradient with respect to the
              spline coefficients, by the forward-mode chain rule.
 
 Every function here is pinned by the CPU tests against closed forms,
 invariants, library routines or brute force; see tests/test_oracle_*.py.
 """
-from . import core, spline, integrate, adjoint, thermostat  # noqa: F401
+from . import core, spline, integrate, adjoint, thermostat, profiles  # noqa: F401

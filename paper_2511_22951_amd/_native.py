@@ -72,6 +72,9 @@ class Walls(C.Structure):
 
 
 MD_MAX_THERMO_REGIONS = 4
+MD_PROF_LEN = 18
+PROF_FIELDS = ("N", "M", "ux", "uy", "uz", "Tx", "Ty", "Tz", "T", "Pxx", "Pyy", "Pzz", "Pxy",
+               "Pxz", "Pyz", "P", "Epot_per_mass", "Eint_per_mass")
 
 
 class ThermoRegion(C.Structure):
@@ -113,6 +116,10 @@ _SIGS = {
     "md_eam_backward": (_i, [_P(Batch), _P(EAM), _i, _vp, _P(NList), _vp, _vp, _vp, _vp, _vp,
                              _vp]),
     "md_backward_workspace_bytes": (_sz, [_P(Batch), _P(EAM)]),
+    "md_atom_observables": (_i, [_P(Batch), _P(EAM), _P(LJ), _vp, _P(NList), _vp, _vp, _vp,
+                                 _vp, _vp]),
+    "md_profile_workspace_bytes": (_sz, [_i]),
+    "md_profiles": (_i, [_P(Batch), _i, _d, _d, _i, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp]),
     "md_read_flags": (_i, [_vp, _P(C.c_int), _vp]),
     "md_clear_flags": (_i, [_vp, _vp]),
     "md_status_string": (C.c_char_p, [_i]),

@@ -333,6 +333,38 @@ def md_verlet_step(st: State, phase, dt, inv_mass, walls=None, half_skin=-1.0, l
           "md_verlet_step")
 
 
+def md_atom_observables(st: State, nl: NeighborList, eam: EAMPotential = None, lj=None,
+                        stream=None):
+    """Per-atom energy [n], pair virial [6, n] and, for EAM, {rhobar, F'} [2, n] (FP64,
+    current atom order) from the current list."""
+    dev = st.pos.device
+    n = st.n
+    e = torch.empty(n, dtype=torch.float64, device=dev)
+    w = torch.empty((6, n), dtype=torch.float64, device=dev)
+    rf = torch.empty((2, n), dtype=torch.float64, device=dev) if eam is not None else None
+    check(N.lib().md_atom_observables(C.byref(st.plan.c),
+                                      C.byref(eam.c) if eam is not None else None,
+                                      C.byref(lj) if lj is not None else None, _ptr(st.pos),
+                                      C.byref(nl.c), _ptr(e), _ptr(w), _ptr(rf), _ptr(st.ctl),
+                                      _stream(stream)), "md_atom_observables")
+    return e, w, rf
+
+
+def md_profiles(st: State, axis, lo, width, n_bins, mass, e_atom=None, w_atom=None, ws=None,
+                stream=None):
+    """Slab profiles [n_bins, MD_PROF_LEN] (fields N.PROF_FIELDS) of a single box."""
+    dev = st.pos.device
+    out = torch.empty((n_bins, N.MD_PROF_LEN), dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = torch.empty(max(256, int(N.lib().md_profile_workspace_bytes(int(n_bins)))),
+                         dtype=torch.uint8, device=dev)
+    check(N.lib().md_profiles(C.byref(st.plan.c), int(axis), float(lo), float(width),
+                              int(n_bins), _ptr(st.pos), _ptr(st.vel), float(mass),
+                              _ptr(e_atom), _ptr(w_atom), _ptr(out), _ptr(ws), _stream(stream)),
+          "md_profiles")
+    return out
+
+
 def md_eam_backward(st: State, pot: EAMPotential, nl: NeighborList, saved, grad_force, ws=None,
                     stream=None):
     """grad_force: [3, n] FP64 cotangent in the current atom order.  Returns [n_coef total]."""

@@ -187,7 +187,8 @@ class Simulation:
 
     # -- results --------------------------------------------------------------
     def energies(self, steps):
-        """(step, PE, KE, W[6]) for the given step numbers (must be within the last ev_cap)."""
+        """Per-step records {E_pot, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz, K} (eV) of the given
+        step numbers (which must be within the last ev_cap)."""
         ev = md.ev_values(self.ev)[:, 0, :]
         rows = [ev[s % self.ev_cap] for s in steps]
         return np.array(rows)
