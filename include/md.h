@@ -340,6 +340,49 @@ int md_eam_backward(const md_batch* b, const md_eam* p, md_precision prec, const
                     double* grad_coef, void* ws, void* ctl, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Behler-Parrinello network potential (Sec. 2.1)
+ * ------------------------------------------------------------------------- */
+
+/* E = sum_i E_i (eq. E_as_sum); E_i is a fully connected network (eq. AtomicNN:
+ * n_g inputs -> h1 tanh -> h2 tanh -> 1 linear) of the symmetry functions of atom i
+ * over its neighbours j within r_cut, f_c(R) = (cos(pi R / r_cut) + 1) / 2:
+ *   G2_mu = sum_j exp(-g2_eta[mu] (R_ij - r_s)^2) f_c(R_ij)                       (eq. G2)
+ *   G4_mu = 2^(1 - zeta) sum_{j != k} (1 + lambda cos theta_ijk)^zeta
+ *           exp(-eta (R_ij^2 + R_ik^2 + R_jk^2)) f_c(R_ij) f_c(R_ik) f_c(R_jk)     (eq. G4)
+ * (the radial exponent read as squared; the angular sum over ordered pairs j != k).
+ * Forces by eq. force, F_k = -sum_i sum_mu dE_i/dG_mu(i) dG_mu(i)/dR_k, with the
+ * network's backward pass and analytic symmetry-function derivatives.  Weights are
+ * one device FP64 array: w01 [n_g][h1], b1 [h1], w12 [h1][h2], b2 [h2], w23 [h2], b3,
+ * row-major, inputs ordered G2 then G4.  At most MD_BPNN_MAX_G inputs, hidden widths
+ * up to MD_BPNN_MAX_HIDDEN, at most 8 distinct G4 eta values and 8 distinct
+ * (zeta, lambda) pairs, zeta >= 1, lambda = +-1. */
+#define MD_BPNN_MAX_G 64
+#define MD_BPNN_MAX_HIDDEN 32
+#define MD_BPNN_MAX_NB 128 /* neighbours within r_cut per atom (MD_FLAG_NEIGH_OVERFLOW) */
+typedef struct md_bpnn {
+  double r_cut, r_s;
+  int n_g2, n_g4, h1, h2;
+  double g2_eta[MD_BPNN_MAX_G];
+  double g4_zeta[MD_BPNN_MAX_G], g4_lambda[MD_BPNN_MAX_G], g4_eta[MD_BPNN_MAX_G];
+  const double* weights; /* device */
+} md_bpnn;
+
+/* Workspace of md_bpnn_forces: (n_g2 + n_g4 + 1) doubles per atom. */
+size_t md_bpnn_workspace_bytes(const md_batch* b, const md_bpnn* p);
+
+/* Energy, forces ([3][n] FP64, overwritten) and virial of the network potential in
+ * FP64 from a list built with r_ns >= r_cut; e_atom [n] (optional) receives E_i.
+ * The record {E, W[6], K} goes to ev[(step % ev_cap) * n_rep + rep] as in
+ * md_lj_forces (W = -sum_i sum (x_j - x_i) (x) dE_i/d(x_j - x_i) over the neighbour
+ * vectors each E_i depends on); with vel the trailing half kick is applied and K
+ * reduced.  Contributions to a neighbour's force are added with FP64 atomics, so
+ * forces can differ from run to run in the last bits (energies and virials are
+ * fixed-point and reproducible). */
+int md_bpnn_forces(const md_batch* b, const md_bpnn* p, const double* pos, const md_nlist* nl,
+                   double* force, double* e_atom, double* vel, double inv_mass, double half_dt,
+                   long long* ev, int ev_cap, void* ws, void* ctl, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Analysis (Appendix)
  * ------------------------------------------------------------------------- */
 

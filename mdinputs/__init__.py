@@ -174,7 +174,7 @@ class MDSystem:
     dt_ps: float
     n_steps: int
     skin: float
-    potential: str               # "lj" or "eam"
+    potential: str               # "lj", "eam" or "bpnn"
     lj: LJParams | None = None
     eam: EAMParams | None = None
     table: EAMTable | None = None
@@ -295,3 +295,41 @@ def random_cotangent(n_atoms: int, seed: int, scale: float = 1.0):
     """Seeded dL/dF cotangent [n_atoms, 3] for vector-Jacobian parity tests."""
     rng = np.random.default_rng(seed)
     return scale * rng.normal(0.0, 1.0, size=(n_atoms, 3))
+
+
+# ----------------------------------------------------------------------------
+# Behler-Parrinello network potential (Sec. 2.1): symmetry-function parameters and
+# random network weights (no trained model ships with the paper)
+# ----------------------------------------------------------------------------
+def bpnn_params(seed: int | None = None, r_cut: float = 6.0, hidden=(10, 10)) -> dict:
+    """8 radial G2 functions (shared R_s = 0, eta spread over 0.003-1.0 / A^2) and 43
+    angular G4 functions (zeta in {1, 2, 4, 16} x lambda in {+1, -1} x eta in
+    {0, 0.003, 0.008, 0.015, 0.03, 0.06} / A^2, the first 43 combinations), as in the
+    MAISE-format models the paper describes (8 G2 + 43 G4 per atom type, two hidden
+    layers of 10); weights N(0, s^2) with s scaled by the fan-in and a rough input
+    magnitude (10 for G2, 100 for G4) so that tanh stays out of saturation."""
+    rng = np.random.default_rng(SEED_BASE + 8 if seed is None else seed)
+    g2_eta = np.array([0.003, 0.01, 0.03, 0.06, 0.12, 0.25, 0.5, 1.0])
+    combos = [(z, l, e) for e in (0.0, 0.003, 0.008, 0.015, 0.03, 0.06)
+              for z in (1.0, 2.0, 4.0, 16.0) for l in (1.0, -1.0)][:43]
+    g4 = np.array(combos)
+    ng = len(g2_eta) + len(g4)
+    h1, h2 = hidden
+    scale_in = np.concatenate([np.full(len(g2_eta), 10.0), np.full(len(g4), 100.0)])
+    w01 = rng.normal(0.0, 1.0, (ng, h1)) / (np.sqrt(ng) * scale_in[:, None])
+    return {
+        "r_cut": r_cut, "r_s": 0.0, "g2_eta": g2_eta,
+        "g4_zeta": g4[:, 0].copy(), "g4_lambda": g4[:, 1].copy(), "g4_eta": g4[:, 2].copy(),
+        "w01": w01, "b1": rng.normal(0.0, 0.1, h1),
+        "w12": rng.normal(0.0, 1.0 / np.sqrt(h1), (h1, h2)), "b2": rng.normal(0.0, 0.1, h2),
+        "w23": rng.normal(0.0, 1.0 / np.sqrt(h2), h2), "b3": -3.5,
+    }
+
+
+def bpnn_copper(cells: int = 8, seed: int | None = None) -> MDSystem:
+    """Copper described by the network potential of bpnn_params (r_c 6 A): fcc cells^3,
+    a = 3.615, N(0, 0.05^2) displacements, 300 K, dt 1 fs, skin 0.3."""
+    pos, box = fcc_lattice(cells, cells, cells, 3.615)
+    x, v = thermal_state(pos, MASS["Cu"], 300.0, 0.05, SEED_BASE + 9 if seed is None else seed)
+    return MDSystem("bpnn_cu_%d" % (4 * cells ** 3), wrap_into_box(x, box), v, box, MASS["Cu"],
+                    1e-3, 100, 0.3, "bpnn", extra={"bpnn": bpnn_params()})

@@ -87,6 +87,16 @@ class Langevin(C.Structure):
                 ("n_regions", C.c_int), ("region", ThermoRegion * MD_MAX_THERMO_REGIONS)]
 
 
+MD_BPNN_MAX_G = 64
+
+
+class BPNN(C.Structure):
+    _fields_ = [("r_cut", C.c_double), ("r_s", C.c_double), ("n_g2", C.c_int), ("n_g4", C.c_int),
+                ("h1", C.c_int), ("h2", C.c_int), ("g2_eta", C.c_double * MD_BPNN_MAX_G),
+                ("g4_zeta", C.c_double * MD_BPNN_MAX_G), ("g4_lambda", C.c_double * MD_BPNN_MAX_G),
+                ("g4_eta", C.c_double * MD_BPNN_MAX_G), ("weights", C.c_void_p)]
+
+
 class Drift(C.Structure):
     _fields_ = [("pos_out", C.c_void_p), ("pos_ref", C.c_void_p), ("dt", C.c_double),
                 ("half_skin", C.c_double), ("walls", Walls)]
@@ -119,6 +129,9 @@ _SIGS = {
     "md_atom_observables": (_i, [_P(Batch), _P(EAM), _P(LJ), _vp, _P(NList), _vp, _vp, _vp,
                                  _vp, _vp]),
     "md_profile_workspace_bytes": (_sz, [_i]),
+    "md_bpnn_workspace_bytes": (_sz, [_P(Batch), _P(BPNN)]),
+    "md_bpnn_forces": (_i, [_P(Batch), _P(BPNN), _vp, _P(NList), _vp, _vp, _vp, _d, _d, _vp, _i,
+                            _vp, _vp, _vp]),
     "md_profiles": (_i, [_P(Batch), _i, _d, _d, _i, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp]),
     "md_read_flags": (_i, [_vp, _P(C.c_int), _vp]),
     "md_clear_flags": (_i, [_vp, _vp]),

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libmd950.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["md_api.hip", "md_neigh.hip", "md_tables.hip", "md_force.hip", "md_verlet.hip",
-           "md_adjoint.hip", "md_profile.hip"]
+           "md_adjoint.hip", "md_profile.hip", "md_bpnn.hip"]
 EXTRA = {"md_neigh.hip": ["-ffp-contract=off"]}
 ARCH = os.environ.get("MD950_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -302,18 +302,7 @@ __device__ __forceinline__ double write_force_kick(int i, int n, R fx, R fy, R f
   return 0.5 / (inv_mass * MD_ACCEL) * (vx * vx + vy * vy + vz * vz);
 }
 
-// Block 0 of the first force kernel of a step: advance the step counter to the
-// value the kick-drift published, and verify the neighbour list: if an atom has
-// moved more than half the skin since the list was built and no rebuild followed,
-// the list may miss pairs (MD_FLAG_STALE_LIST).
-__device__ __forceinline__ void step_bookkeeping(md_ctl_dev* ctl) {
-  if (blockIdx.x != 0) return;
-  const bool stale = md_displacement_exceeded(ctl);
-  if (threadIdx.x == 0) {
-    if (stale) md_flag(ctl, MD_FLAG_STALE_LIST);
-    ctl->step = ctl->step_next;
-  }
-}
+__device__ __forceinline__ void step_bookkeeping(md_ctl_dev* ctl) { md_step_bookkeeping(ctl); }
 
 // ---------------------------------------------------------------------------
 // EAM pass 1: rhobar_i = sum_j rho(r_ij), F'(rhobar_i) into pos[i].w, energy.

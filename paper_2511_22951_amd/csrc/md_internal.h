@@ -44,6 +44,21 @@ __device__ __forceinline__ bool md_displacement_exceeded(const md_ctl_dev* ctl) 
   return __syncthreads_or(over) != 0;
 }
 
+__device__ __forceinline__ void md_flag(md_ctl_dev* ctl, int bits);
+
+// Block 0 of the first force kernel of a step: advance the step counter to the
+// value the kick-drift published, and verify the neighbour list: if an atom has
+// moved more than half the skin since the list was built and no rebuild followed,
+// the list may miss pairs (MD_FLAG_STALE_LIST).
+__device__ __forceinline__ void md_step_bookkeeping(md_ctl_dev* ctl) {
+  if (blockIdx.x != 0) return;
+  const bool stale = md_displacement_exceeded(ctl);
+  if (threadIdx.x == 0) {
+    if (stale) md_flag(ctl, MD_FLAG_STALE_LIST);
+    ctl->step = ctl->step_next;
+  }
+}
+
 // Offsets of the workspace regions (bytes, 256-aligned).
 struct md_ws_layout {
   size_t cell_of, rank, src, sid, counts, scan, pos_s, vel_s, id_s, partial, total;

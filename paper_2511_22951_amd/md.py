@@ -333,6 +333,55 @@ def md_verlet_step(st: State, phase, dt, inv_mass, walls=None, half_skin=-1.0, l
           "md_verlet_step")
 
 
+class BPNNPotential:
+    """md_bpnn: symmetry-function parameters by value and the network weights on the
+    device ({"r_cut", "r_s", "g2_eta", "g4_zeta", "g4_lambda", "g4_eta", "w01", "b1",
+    "w12", "b2", "w23", "b3"})."""
+
+    def __init__(self, params, device="cuda"):
+        w01 = np.asarray(params["w01"], np.float64)
+        ng, h1 = w01.shape
+        w12 = np.asarray(params["w12"], np.float64)
+        h2 = w12.shape[1]
+        n2, n4 = len(params["g2_eta"]), len(params["g4_eta"])
+        if n2 + n4 != ng or w12.shape[0] != h1:
+            raise ValueError("network shapes do not match the symmetry functions")
+        flat = np.concatenate([w01.ravel(), np.asarray(params["b1"], np.float64).ravel(),
+                               w12.ravel(), np.asarray(params["b2"], np.float64).ravel(),
+                               np.asarray(params["w23"], np.float64).ravel(),
+                               np.atleast_1d(np.asarray(params["b3"], np.float64))])
+        self.weights = torch.from_numpy(flat).to(device)
+        c = N.BPNN()
+        c.r_cut, c.r_s = float(params["r_cut"]), float(params["r_s"])
+        c.n_g2, c.n_g4, c.h1, c.h2 = n2, n4, h1, h2
+        for k in range(n2):
+            c.g2_eta[k] = float(params["g2_eta"][k])
+        for k in range(n4):
+            c.g4_zeta[k] = float(params["g4_zeta"][k])
+            c.g4_lambda[k] = float(params["g4_lambda"][k])
+            c.g4_eta[k] = float(params["g4_eta"][k])
+        c.weights = self.weights.data_ptr()
+        self.c = c
+        self.r_cut = c.r_cut
+
+
+def md_bpnn_forces(st: State, pot: BPNNPotential, nl: NeighborList, inv_mass=0.0, half_dt=0.0,
+                   kick=False, ev=None, ev_cap=1, e_atom=None, ws=None, stream=None):
+    """Network-potential forces into st.force (FP64); ws: md_bpnn_workspace_bytes bytes."""
+    if st.force.dtype != torch.float64:
+        raise ValueError("the network potential computes FP64 forces")
+    if ws is None:
+        ws = torch.empty(max(256, int(N.lib().md_bpnn_workspace_bytes(C.byref(st.plan.c),
+                                                                         C.byref(pot.c)))),
+                         dtype=torch.uint8, device=st.pos.device)
+    vel = st.vel if kick else None
+    check(N.lib().md_bpnn_forces(C.byref(st.plan.c), C.byref(pot.c), _ptr(st.pos), C.byref(nl.c),
+                                 _ptr(st.force), _ptr(e_atom), _ptr(vel), float(inv_mass),
+                                 float(half_dt), _ptr(ev), int(ev_cap), _ptr(ws), _ptr(st.ctl),
+                                 _stream(stream)), "md_bpnn_forces")
+    return ws
+
+
 def md_atom_observables(st: State, nl: NeighborList, eam: EAMPotential = None, lj=None,
                         stream=None):
     """Per-atom energy [n], pair virial [6, n] and, for EAM, {rhobar, F'} [2, n] (FP64,

@@ -42,13 +42,18 @@ class Simulation:
                  device="cuda", table=None, rebuild_every=0, fused=False, thermostat=None):
         self.sys = system
         # the Langevin update runs in the kick-drift kernel, so it is not fused
-        self.fused = bool(fused) and system.potential != "lj" and thermostat is None
+        self.fused = bool(fused) and system.potential == "eam" and thermostat is None
         self.primed = False  # fused: the last force pass already did the next kick-drift
         self.pos_alt = None
         self.rebuild_every = int(rebuild_every)
         self.n_steps = 0
         self.precision = precision
-        r_cut = system.lj.r_cut if system.potential == "lj" else system.eam.r_cut
+        if system.potential == "lj":
+            r_cut = system.lj.r_cut
+        elif system.potential == "bpnn":
+            r_cut = system.extra["bpnn"]["r_cut"]
+        else:
+            r_cut = system.eam.r_cut
         self.r_ns = r_cut + system.skin
         self.plan = md.Plan([system.box], [system.pos.shape[0]], self.r_ns, device)
         self.state = md.State(self.plan, system.pos, system.vel, precision)
@@ -60,8 +65,15 @@ class Simulation:
         self.langevin = md.langevin_params(self.state, thermostat)
         self.ev_cap = ev_cap
         self.ev = md.ev_buffer(ev_cap, 1, device)
+        self.bpnn = None
         if system.potential == "lj":
             self.lj = md.lj_params(system.lj.eps, system.lj.sigma, system.lj.r_cut)
+            self.pot = None
+        elif system.potential == "bpnn":
+            if precision != N.MD_FP64:
+                raise ValueError("the network potential runs in FP64")
+            self.bpnn = md.BPNNPotential(system.extra["bpnn"], device)
+            self.bpnn_ws = None
             self.pot = None
         else:
             self.pot = md.EAMPotential.from_table(table or system.table, device)
@@ -74,7 +86,11 @@ class Simulation:
         st = self.state
         half_dt = 0.5 * self.dt if kick else 0.0
         evb = self.ev if ev else None
-        if self.pot is None:
+        if self.bpnn is not None:
+            self.bpnn_ws = md.md_bpnn_forces(st, self.bpnn, self.nl, self.inv_mass, half_dt,
+                                             kick=True, ev=evb, ev_cap=self.ev_cap,
+                                             ws=self.bpnn_ws)
+        elif self.pot is None:
             md.md_lj_forces(st, self.lj, self.nl, self.inv_mass, half_dt, kick=True, ev=evb,
                             ev_cap=self.ev_cap)
         else:
