@@ -48,12 +48,12 @@ def parse():
                     help="only copy MIB MiB device to device a few times (the known-size "
                          "transfer that scales the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--workload", choices=["cu131k", "al_shock", "cold_curve", "force_matching",
-                                           "lj13m", "nvt"],
+                                           "lj13m", "nvt", "bpnn"],
                     default="cu131k",
                     help="cu131k: the headline EAM Cu NVE run; the others are the secondary "
                          "measurements (640k-atom Al shock, 64 batched cold-curve replicas, "
                          "force-matching epochs, the 13M-atom LJ test of Sec. 1.7, Cu with a "
-                         "Langevin thermostat)")
+                         "Langevin thermostat, Cu with the network potential)")
     ap.add_argument("--unfused", action="store_true",
                     help="run the kick-drift as its own pass instead of fusing it into the force "
                          "pass")
@@ -255,7 +255,7 @@ def main():
     if args.workload != "cu131k":
         {"al_shock": bench_al_shock, "cold_curve": bench_cold_curve,
          "force_matching": bench_force_matching, "lj13m": bench_lj_paper,
-         "nvt": bench_nvt}[args.workload](args)
+         "nvt": bench_nvt, "bpnn": bench_bpnn}[args.workload](args)
         return
     import torch
     import mdinputs as mi
@@ -577,6 +577,76 @@ def bench_nvt(args):
                      "kernel": "k_kick_drift (Langevin)",
                      "kernel_us": res["nvt"]["kick_drift_us"], "bytes_per_launch": kd_bytes},
         "paths": res,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def bench_bpnn(args):
+    """Behler-Parrinello network potential (Sec. 2.1) on Cu fcc 32^3 = 131,072 atoms, FP64:
+    NVE steps with threshold rebuilds, HIP-graph replay."""
+    import torch
+    import mdinputs as mi
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    N.lib()
+    system = mi.bpnn_copper(cells=32)
+    n = system.pos.shape[0]
+    steps = args.steps or 100
+    warm = min(args.warmup, 20)
+    gs = min(args.graph_steps, 10)
+    lanes = args.lanes or 4
+    sim = Simulation(system, precision=N.MD_FP64, lanes=lanes, ev_cap=warm + steps + 64).setup()
+    sim.run(warm, graph_steps=gs)
+    torch.cuda.synchronize()
+    st0 = sim.state.read_flags()[1]
+    ms = _gpu_time(lambda: sim.run(steps, graph_steps=gs), 1)
+    status, info = sim.state.read_flags()
+    N.check(status, "device flags after the timed run")
+    ev = sim.energies(range(st0["step"] + 1, info["step"] + 1))
+    etot = (ev[:, 0] + ev[:, 7]) / n
+    kt = {k: 1e3 * time_kernel(N, k, lambda: sim.step(), 5)[0] for k in ("bpnn_desc", "bpnn_force")}
+    # ordered neighbour pairs within r_c (the angular terms' work), counted from the list
+    # (which holds the neighbours within r_c + skin) at the final positions
+    x = sim.state.pos[:, :3]
+    p = system.extra["bpnn"]
+    nn = sim.nl.lengths().double().mean().item()
+    lst = sim.nl
+    raw = lst.neigh.view(lst.max_neigh // lst.lanes, lst.npad, lst.lanes)
+    cnt = lst.lengths().long()
+    m = torch.arange(lst.max_neigh, device="cuda")
+    ent = raw[m // lst.lanes][:, :n, :].gather(2, (m % lst.lanes).view(-1, 1, 1).expand(-1, n, 1))
+    ent = ent.squeeze(2).t()  # [n, max_neigh]
+    valid = m.view(1, -1) < cnt.view(-1, 1)
+    d = x[ent.clamp(min=0).long()] - x.view(n, 1, 3)
+    ln = torch.tensor(system.box.len, dtype=torch.float64, device="cuda")
+    d -= ln * torch.round(d / ln)
+    within = ((d * d).sum(-1) < p["r_cut"] ** 2) & valid
+    m_rc = within.sum(1).double()
+    pairs = float((m_rc * (m_rc - 1.0)).sum().item())
+    grid = len(p["g4_eta"])
+    flops = pairs * grid * (2 + 7)  # grid multiply-adds of the two passes per ordered pair
+    t_s = (kt["bpnn_desc"] + kt["bpnn_force"]) * 1e-6
+    achieved = flops / t_s / 1e12
+    out = {
+        "metric": "atom-steps/s (Cu, Behler-Parrinello network potential, FP64)",
+        "value": n * steps / (ms * 1e-3), "unit": "atom-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (random network weights)",
+        "config": {"workload": "Cu fcc 32^3 = 131072 atoms, a 3.615, 300 K, dt 1 fs, r_c 6, "
+                               "skin 0.3, 8 G2 + 43 G4, network 51-10-10-1 (tanh)",
+                   "n_atoms": n, "lanes_per_atom": lanes, "graph_steps": gs},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "k_bpnn_desc + k_bpnn_force",
+                     "kernel_us": kt["bpnn_desc"] + kt["bpnn_force"],
+                     "flops_per_launch": flops},
+        "kernel_us": kt, "mean_list_len": nn, "ordered_pairs_per_atom": pairs / n,
+        "nve_energy_span_eV_per_atom": float(etot.max() - etot.min()),
+        "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"],
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

@@ -441,6 +441,8 @@ int md_clear_flags(void* ctl, void* stream);
 #define MD_KERNEL_EAM_FORCE 5
 #define MD_KERNEL_KICK_DRIFT 6
 #define MD_KERNEL_EAM_ADJOINT 7
+#define MD_KERNEL_BPNN_DESC 8
+#define MD_KERNEL_BPNN_FORCE 9
 int md_timer_arm(int kernel);
 int md_timer_read(float* ms);
 

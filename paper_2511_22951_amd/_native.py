@@ -141,7 +141,7 @@ _SIGS = {
 }
 
 MD_KERNEL = {"bin_count": 1, "build": 2, "lj": 3, "eam_density": 4, "eam_force": 5,
-             "kick_drift": 6, "eam_adjoint": 7}
+             "kick_drift": 6, "eam_adjoint": 7, "bpnn_desc": 8, "bpnn_force": 9}
 
 EXPORTED = tuple(_SIGS)
 

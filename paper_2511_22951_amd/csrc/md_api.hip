@@ -26,7 +26,7 @@ bool md_timer_take(int kernel, hipEvent_t* start, hipEvent_t* stop) {
 }
 
 extern "C" int md_timer_arm(int kernel) {
-  if (kernel < MD_KERNEL_BIN_COUNT || kernel > MD_KERNEL_EAM_ADJOINT) return MD_ERR_ARG;
+  if (kernel < MD_KERNEL_BIN_COUNT || kernel > MD_KERNEL_BPNN_FORCE) return MD_ERR_ARG;
   if (!g_timer.start) {
     if (hipEventCreate(&g_timer.start) != hipSuccess) return MD_ERR_HIP;
     if (hipEventCreate(&g_timer.stop) != hipSuccess) return MD_ERR_HIP;

@@ -2,8 +2,9 @@
 // the atomic network with its backward pass, and forces by the chain rule (eq. force).
 //
 // One wavefront per atom.  Its neighbours within r_cut are compacted into LDS; the
-// radial functions take lanes over neighbours, the angular ones lanes over the
-// second neighbour k of an ordered pair (j, k).  The G4 set is a grid of distinct
+// radial functions take lanes over neighbours, the angular ones lanes over the flat
+// index of the unordered pairs j < k (the summand is symmetric in j and k, so each
+// unordered pair stands for both ordered ones).  The G4 set is a grid of distinct
 // eta values (index u) and distinct (zeta, lambda) pairs (index v): per pair the
 // lane evaluates exp(-eta_u s2) and (1 + lambda_v cos)^zeta_v once each and
 // accumulates their products on the grid, so the cost per pair does not grow with
@@ -136,6 +137,19 @@ __device__ __forceinline__ Trip triplet(const BpnnDev& P, const Nb& s, int j, in
   return t;
 }
 
+// Unordered pair t (0 <= t < nc (nc - 1) / 2) -> (j, k), j < k, row-major over j:
+// row j holds the nc - 1 - j pairs (j, j + 1 .. nc - 1) and starts at
+// off(j) = j (2 nc - j - 1) / 2.
+__device__ __forceinline__ void pair_of(int t, int nc, int& j, int& k) {
+  const double b = 2.0 * nc - 1.0;
+  int r = (int)floor(0.5 * (b - sqrt(b * b - 8.0 * (double)t)));
+  r = r < 0 ? 0 : (r > nc - 2 ? nc - 2 : r);
+  while (r > 0 && r * (2 * nc - r - 1) / 2 > t) --r;
+  while (r < nc - 2 && (r + 1) * (2 * nc - r - 2) / 2 <= t) ++r;
+  j = r;
+  k = t - r * (2 * nc - r - 1) / 2 + r + 1;
+}
+
 // Pass 1: symmetry functions, E_i and dE_i/dG per atom.
 __global__ __launch_bounds__(64 * WPB) void k_bpnn_desc(md_batch b, BpnnDev P, const double4* pos,
                                                         md_nlist nl, size_t npad, double* dEdG,
@@ -161,15 +175,17 @@ __global__ __launch_bounds__(64 * WPB) void k_bpnn_desc(md_batch b, BpnnDev P, c
       acc = md_wave_sum(acc);
       if (lane == 0) s.G[mu] = acc;
     }
-    // angular functions: ordered pairs (j, k != j), lanes over k
+    // angular functions: lanes over the unordered pairs
     double g[NE][NZ];
 #pragma unroll
     for (int u = 0; u < NE; ++u)
 #pragma unroll
       for (int v = 0; v < NZ; ++v) g[u][v] = 0.0;
-    for (int j = 0; j < nc; ++j) {
-      for (int k = lane; k < nc; k += MD_WAVE) {
-        if (k == j) continue;
+    const int npairs = nc * (nc - 1) / 2;
+    for (int tp = lane; tp < npairs; tp += MD_WAVE) {
+      {
+        int j, k;
+        pair_of(tp, nc, j, k);
         const Trip t = triplet(P, s, j, k);
         if (t.f3 == 0.0) continue;
         double X[NE], Pw[NZ];
@@ -195,7 +211,7 @@ __global__ __launch_bounds__(64 * WPB) void k_bpnn_desc(md_batch b, BpnnDev P, c
 #pragma unroll
         for (int v = 0; v < NZ; ++v)
           if (u == P.u_of[lane] && v == P.v_of[lane]) val = g[u][v];
-      s.G[P.n2 + lane] = P.pref[lane] * val;
+      s.G[P.n2 + lane] = 2.0 * P.pref[lane] * val;  // both orders of each pair
     }
     __builtin_amdgcn_wave_barrier();
     // the atomic network and its backward pass
@@ -284,7 +300,8 @@ __global__ __launch_bounds__(64 * WPB) void k_bpnn_force(md_batch b, BpnnDev P,
     for (int q = lane; q < NE * NZ; q += MD_WAVE) s.C[q] = 0.0;
     __builtin_amdgcn_wave_barrier();
     if (lane == 0)
-      for (int q = 0; q < P.n4; ++q) s.C[P.u_of[q] * NZ + P.v_of[q]] += c[P.n2 + q] * P.pref[q];
+      for (int q = 0; q < P.n4; ++q)
+        s.C[P.u_of[q] * NZ + P.v_of[q]] += 2.0 * c[P.n2 + q] * P.pref[q];  // both orders
     __builtin_amdgcn_wave_barrier();
     // radial terms: lanes over neighbours
     for (int m = lane; m < nc; m += MD_WAVE) {
@@ -300,65 +317,60 @@ __global__ __launch_bounds__(64 * WPB) void k_bpnn_force(md_batch b, BpnnDev P,
       s.gz[m] += q * s.az[m];
     }
     __builtin_amdgcn_wave_barrier();
-    // angular terms: ordered pairs (j, k != j), lanes over k
-    for (int j = 0; j < nc; ++j) {
-      double gaj[3] = {0, 0, 0};
-      for (int k = lane; k < nc; k += MD_WAVE) {
-        if (k == j) continue;
-        const Trip t = triplet(P, s, j, k);
-        if (t.f3 == 0.0 && t.fC * s.fc[j] * s.dfc[k] == 0.0 && t.fC * s.dfc[j] * s.fc[k] == 0.0 &&
-            s.fc[j] * s.fc[k] * t.dfC == 0.0)
-          continue;
-        double X[NE], Pw[NZ], Pw1[NZ];
+    // angular terms: lanes over the unordered pairs j < k.  The pair (j, k) adds g_a to
+    // neighbour j and g_b to k; the reversed order adds the same vectors with the
+    // roles swapped, which the factor 2 in the grid weights C accounts for.  Lanes of
+    // one step can share a neighbour, so the LDS sums take atomic adds.
+    const int npairs = nc * (nc - 1) / 2;
+    for (int tp = lane; tp < npairs; tp += MD_WAVE) {
+      int j, k;
+      pair_of(tp, nc, j, k);
+      const Trip t = triplet(P, s, j, k);
+      if (t.fC == 0.0 && t.dfC == 0.0) continue;  // R_jk >= r_cut: no term, no derivative
+      double X[NE], Pw[NZ], Pw1[NZ];
 #pragma unroll
-        for (int u = 0; u < NE; ++u) X[u] = u < P.n_eta ? exp(-P.eta_u[u] * t.s2) : 0.0;
-        const double cz = t.cos;
+      for (int u = 0; u < NE; ++u) X[u] = u < P.n_eta ? exp(-P.eta_u[u] * t.s2) : 0.0;
+      const double cz = t.cos;
+#pragma unroll
+      for (int v = 0; v < NZ; ++v) {
+        const double base = 1.0 + P.lam_v[v] * cz;
+        const int iz = P.izeta_v[v];
+        Pw1[v] = v < P.n_zl ? powi(base, iz > 0 ? iz - 1 : 0, P.zeta_v[v] - 1.0) : 0.0;
+        Pw[v] = Pw1[v] * base;
+      }
+      double q1 = 0.0, qe = 0.0, qc = 0.0;
+#pragma unroll
+      for (int u = 0; u < NE; ++u)
 #pragma unroll
         for (int v = 0; v < NZ; ++v) {
-          const double base = 1.0 + P.lam_v[v] * cz;
-          const int iz = P.izeta_v[v];
-          Pw1[v] = v < P.n_zl ? powi(base, iz > 0 ? iz - 1 : 0, P.zeta_v[v] - 1.0) : 0.0;
-          Pw[v] = Pw1[v] * base;
+          const double cw = s.C[u * NZ + v] * X[u];
+          q1 += cw * Pw[v];
+          qe += cw * Pw[v] * P.eta_u[u];
+          qc += cw * P.zeta_v[v] * P.lam_v[v] * Pw1[v];
         }
-        double q1 = 0.0, qe = 0.0, qc = 0.0;
+      const double A = s.R[j], B = s.R[k], Cd = t.C;
+      const double fA = s.fc[j], dfA = s.dfc[j], fB = s.fc[k], dfB = s.dfc[k];
+      const double s_cos = qc * t.f3;
+      const double sA = q1 * dfA * fB * t.fC - 2.0 * A * qe * t.f3;
+      const double sB = q1 * fA * dfB * t.fC - 2.0 * B * qe * t.f3;
+      const double sC = q1 * fA * fB * t.dfC - 2.0 * Cd * qe * t.f3;
+      const double aj[3] = {s.ax[j], s.ay[j], s.az[j]}, ak[3] = {s.ax[k], s.ay[k], s.az[k]};
+      const double iAB = 1.0 / (A * B), cA = t.cos / (A * A), cB = t.cos / (B * B);
+      double ga[3], gb[3];
 #pragma unroll
-        for (int u = 0; u < NE; ++u)
-#pragma unroll
-          for (int v = 0; v < NZ; ++v) {
-            const double cw = s.C[u * NZ + v] * X[u];
-            q1 += cw * Pw[v];
-            qe += cw * Pw[v] * P.eta_u[u];
-            qc += cw * P.zeta_v[v] * P.lam_v[v] * Pw1[v];
-          }
-        const double A = s.R[j], B = s.R[k], Cd = t.C;
-        const double fA = s.fc[j], dfA = s.dfc[j], fB = s.fc[k], dfB = s.dfc[k];
-        const double s_cos = qc * t.f3;
-        const double sA = q1 * dfA * fB * t.fC - 2.0 * A * qe * t.f3;
-        const double sB = q1 * fA * dfB * t.fC - 2.0 * B * qe * t.f3;
-        const double sC = q1 * fA * fB * t.dfC - 2.0 * Cd * qe * t.f3;
-        const double aj[3] = {s.ax[j], s.ay[j], s.az[j]}, ak[3] = {s.ax[k], s.ay[k], s.az[k]};
-        const double iAB = 1.0 / (A * B), cA = t.cos / (A * A), cB = t.cos / (B * B);
-        double gb[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const double d = ak[q] - aj[q];
-          gaj[q] += s_cos * (ak[q] * iAB - cA * aj[q]) + sA / A * aj[q] - sC / Cd * d;
-          gb[q] = s_cos * (aj[q] * iAB - cB * ak[q]) + sB / B * ak[q] + sC / Cd * d;
-        }
-        s.gx[k] += gb[0];
-        s.gy[k] += gb[1];
-        s.gz[k] += gb[2];
+      for (int q = 0; q < 3; ++q) {
+        const double d = ak[q] - aj[q];
+        ga[q] = s_cos * (ak[q] * iAB - cA * aj[q]) + sA / A * aj[q] - sC / Cd * d;
+        gb[q] = s_cos * (aj[q] * iAB - cB * ak[q]) + sB / B * ak[q] + sC / Cd * d;
       }
-#pragma unroll
-      for (int q = 0; q < 3; ++q) gaj[q] = md_wave_sum(gaj[q]);
-      __builtin_amdgcn_wave_barrier();
-      if (lane == 0) {
-        s.gx[j] += gaj[0];
-        s.gy[j] += gaj[1];
-        s.gz[j] += gaj[2];
-      }
-      __builtin_amdgcn_wave_barrier();
+      atomicAdd(&s.gx[j], ga[0]);
+      atomicAdd(&s.gy[j], ga[1]);
+      atomicAdd(&s.gz[j], ga[2]);
+      atomicAdd(&s.gx[k], gb[0]);
+      atomicAdd(&s.gy[k], gb[1]);
+      atomicAdd(&s.gz[k], gb[2]);
     }
+    __builtin_amdgcn_wave_barrier();
     // scatter: F_j -= g, F_i += sum g, W -= a (x) g
     double fi[3] = {0, 0, 0}, wv[6] = {0, 0, 0, 0, 0, 0};
     for (int m = lane; m < nc; m += MD_WAVE) {
@@ -504,12 +516,12 @@ extern "C" int md_bpnn_forces(const md_batch* b, const md_bpnn* p, const double*
   hipLaunchKernelGGL(k_bpnn_zero, dim3(1024), dim3(256), 0, st, *b, force, (long long*)ev, ev_cap,
                      c);
   MD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bpnn_desc, dim3(b->n_tiles), dim3(64 * WPB), 0, st, *b, P,
-                     (const double4*)pos, *nl, npad, dEdG, e_buf, c);
+  MD_LAUNCH_TIMED(MD_KERNEL_BPNN_DESC, k_bpnn_desc, dim3(b->n_tiles), dim3(64 * WPB), 0, st, *b,
+                  P, (const double4*)pos, *nl, npad, dEdG, e_buf, c);
   MD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bpnn_force, dim3(b->n_tiles), dim3(64 * WPB), 0, st, *b, P,
-                     (const double4*)pos, *nl, npad, (const double*)dEdG, (const double*)e_buf,
-                     force, (long long*)ev, ev_cap, c);
+  MD_LAUNCH_TIMED(MD_KERNEL_BPNN_FORCE, k_bpnn_force, dim3(b->n_tiles), dim3(64 * WPB), 0, st, *b,
+                  P, (const double4*)pos, *nl, npad, (const double*)dEdG, (const double*)e_buf,
+                  force, (long long*)ev, ev_cap, c);
   MD_LAUNCH_CHECK();
   if (vel) {
     const int nb = (b->n_tiles + MD_ATOM_BLOCK / MD_WAVE - 1) / (MD_ATOM_BLOCK / MD_WAVE);
