@@ -150,8 +150,11 @@ __device__ __forceinline__ void pair_of(int t, int nc, int& j, int& k) {
   k = t - r * (2 * nc - r - 1) / 2 + r + 1;
 }
 
-// Pass 1: symmetry functions, E_i and dE_i/dG per atom.
-__global__ __launch_bounds__(64 * WPB) void k_bpnn_desc(md_batch b, BpnnDev P, const double4* pos,
+// Pass 1: symmetry functions, E_i and dE_i/dG per atom.  NEU eta values are kept in the
+// per-lane accumulator grid (NEU x NZ registers): 6 for sets with at most six distinct
+// eta values (the common case, which leaves room for two wavefronts per SIMD), else NE.
+template <int NEU>
+__global__ __launch_bounds__(64 * WPB, 2) void k_bpnn_desc(md_batch b, BpnnDev P, const double4* pos,
                                                         md_nlist nl, size_t npad, double* dEdG,
                                                         double* e_buf, md_ctl_dev* ctl) {
   __shared__ Nb sh[WPB];
@@ -176,9 +179,9 @@ __global__ __launch_bounds__(64 * WPB) void k_bpnn_desc(md_batch b, BpnnDev P, c
       if (lane == 0) s.G[mu] = acc;
     }
     // angular functions: lanes over the unordered pairs
-    double g[NE][NZ];
+    double g[NEU][NZ];
 #pragma unroll
-    for (int u = 0; u < NE; ++u)
+    for (int u = 0; u < NEU; ++u)
 #pragma unroll
       for (int v = 0; v < NZ; ++v) g[u][v] = 0.0;
     const int npairs = nc * (nc - 1) / 2;
@@ -188,26 +191,26 @@ __global__ __launch_bounds__(64 * WPB) void k_bpnn_desc(md_batch b, BpnnDev P, c
         pair_of(tp, nc, j, k);
         const Trip t = triplet(P, s, j, k);
         if (t.f3 == 0.0) continue;
-        double X[NE], Pw[NZ];
+        double X[NEU], Pw[NZ];
 #pragma unroll
-        for (int u = 0; u < NE; ++u) X[u] = u < P.n_eta ? exp(-P.eta_u[u] * t.s2) * t.f3 : 0.0;
+        for (int u = 0; u < NEU; ++u) X[u] = u < P.n_eta ? exp(-P.eta_u[u] * t.s2) * t.f3 : 0.0;
 #pragma unroll
         for (int v = 0; v < NZ; ++v)
           Pw[v] = v < P.n_zl ? powi(1.0 + P.lam_v[v] * t.cos, P.izeta_v[v], P.zeta_v[v]) : 0.0;
 #pragma unroll
-        for (int u = 0; u < NE; ++u)
+        for (int u = 0; u < NEU; ++u)
 #pragma unroll
           for (int v = 0; v < NZ; ++v) g[u][v] += X[u] * Pw[v];
       }
     }
 #pragma unroll
-    for (int u = 0; u < NE; ++u)
+    for (int u = 0; u < NEU; ++u)
 #pragma unroll
       for (int v = 0; v < NZ; ++v) g[u][v] = md_wave_sum(g[u][v]);
     if (lane < P.n4) {
       double val = 0.0;
 #pragma unroll
-      for (int u = 0; u < NE; ++u)
+      for (int u = 0; u < NEU; ++u)
 #pragma unroll
         for (int v = 0; v < NZ; ++v)
           if (u == P.u_of[lane] && v == P.v_of[lane]) val = g[u][v];
@@ -276,7 +279,7 @@ __device__ __forceinline__ void block_record_add(double (&v)[7], double* red, lo
 
 // Pass 2: forces.  g_m = dE_i/d a_m for every neighbour vector a_m = x_j - x_i;
 // F_j -= g_m, F_i += sum_m g_m, W -= a_m (x) g_m.
-__global__ __launch_bounds__(64 * WPB) void k_bpnn_force(md_batch b, BpnnDev P,
+__global__ __launch_bounds__(64 * WPB, 3) void k_bpnn_force(md_batch b, BpnnDev P,
                                                          const double4* pos, md_nlist nl,
                                                          size_t npad, const double* dEdG,
                                                          const double* e_buf, double* force,
@@ -516,8 +519,12 @@ extern "C" int md_bpnn_forces(const md_batch* b, const md_bpnn* p, const double*
   hipLaunchKernelGGL(k_bpnn_zero, dim3(1024), dim3(256), 0, st, *b, force, (long long*)ev, ev_cap,
                      c);
   MD_LAUNCH_CHECK();
-  MD_LAUNCH_TIMED(MD_KERNEL_BPNN_DESC, k_bpnn_desc, dim3(b->n_tiles), dim3(64 * WPB), 0, st, *b,
-                  P, (const double4*)pos, *nl, npad, dEdG, e_buf, c);
+  if (P.n_eta <= 6)
+    MD_LAUNCH_TIMED(MD_KERNEL_BPNN_DESC, k_bpnn_desc<6>, dim3(b->n_tiles), dim3(64 * WPB), 0, st,
+                    *b, P, (const double4*)pos, *nl, npad, dEdG, e_buf, c);
+  else
+    MD_LAUNCH_TIMED(MD_KERNEL_BPNN_DESC, k_bpnn_desc<NE>, dim3(b->n_tiles), dim3(64 * WPB), 0, st,
+                    *b, P, (const double4*)pos, *nl, npad, dEdG, e_buf, c);
   MD_LAUNCH_CHECK();
   MD_LAUNCH_TIMED(MD_KERNEL_BPNN_FORCE, k_bpnn_force, dim3(b->n_tiles), dim3(64 * WPB), 0, st, *b,
                   P, (const double4*)pos, *nl, npad, (const double*)dEdG, (const double*)e_buf,
