@@ -458,13 +458,19 @@ def bench_lj_paper(args):
     warm = max(k, args.warmup // k * k)
     sample = np.random.default_rng(7).choice(n, 256, replace=False)
     paths, f_gpu = {}, {}
+    from paper_2511_22951_amd import tune
+    from paper_2511_22951_amd.sim import fused_grid_fits
+    n_tiles = sum((c + 63) // 64 for c in [n])
     for name, prec in (("fp32", N.MD_FP32), ("fp64", N.MD_FP64)):
         if args.precision not in ("both", name):
             continue
-        lanes = args.lanes or autotune_lanes(system, prec)
+        # the fused kick-drift needs a force-pass grid within its displacement slots
+        cands = tuple(l for l in tune.CANDIDATES
+                      if args.unfused or fused_grid_fits(n_tiles, l))
+        lanes = args.lanes or tune.best_lanes(system, prec, candidates=cands)
         cap = warm + steps + args.kernel_samples + 8
         sim = Simulation(system, precision=prec, lanes=lanes, max_neigh=112, ev_cap=cap,
-                         rebuild_every=k).setup()
+                         rebuild_every=k, fused=not args.unfused).setup()
         f_gpu[name] = sim.state.forces()[sample]
         sim.run(warm, graph_steps=gs)
         torch.cuda.synchronize()
@@ -475,11 +481,14 @@ def bench_lj_paper(args):
         ev = sim.energies(range(st0["step"], info["step"] + 1))
         etot = (ev[:, 0] + ev[:, 7]) / n
         kt = {kn: 1e3 * time_kernel(N, kn, lambda: sim.step(), args.kernel_samples // 5)[0]
-              for kn in ("lj", "kick_drift")}
+              for kn in ("lj",) + (() if sim.fused else ("kick_drift",))}
         kt["build"] = 1e3 * time_kernel(N, "build", lambda: sim.rebuild(), 3)[0]
         nn = sim.nl.lengths().double()
         force_bytes = 4 if prec == N.MD_FP32 else 8
-        per_atom = 4.0 + 4.0 * nn.mean().item() + 32.0 + 3.0 * force_bytes + 48.0
+        # list length 4 + list 4 n + own record 32 + force + v read/write 48; with the next
+        # kick-drift fused in, x_ref 24 and the new position record 32
+        per_atom = (4.0 + 4.0 * nn.mean().item() + 32.0 + 3.0 * force_bytes + 48.0
+                    + (56.0 if sim.fused else 0.0))
         paths[name] = {
             "atom_steps_per_s": n * steps / (ms * 1e-3), "ms_per_step": ms / steps,
             "lanes": lanes, "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"],

@@ -275,23 +275,19 @@ int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos, double* v
 int md_build_neighbors(const md_batch* b, md_rebuild_mode mode, const double* pos,
                        const int* cell_start, const md_nlist* nl, void* ctl, void* stream);
 
-/* Lennard-Jones forces (eq. 1.6), energy and virial.  force is [3][n] FP64 or
- * FP32.  If vel is not NULL the trailing half kick v += half_dt f / m is applied
- * and the kinetic energy is reduced.  If ev is not NULL the per-box record
- * {E, W[6], K} is written to ev[(step % ev_cap) * n_rep + rep] (step = the
- * control block's step counter). */
-int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec, const double* pos,
-                 const md_nlist* nl, void* force, double* vel, double inv_mass, double half_dt,
-                 long long* ev, int ev_cap, void* ws, void* ctl, void* stream);
-
-/* The next step's kick-drift fused into the EAM force pass: after the trailing
+/* The next step's kick-drift fused into a force pass (md_lj_forces, md_eam_forces):
+ * after the trailing
  * half kick of step n, v += dt/2 f/m and x_out = x + dt v with the walls at
  * t = (step + 1) dt, then the half-skin displacement check against pos_ref --
  * the same operations, in the same order, as md_verlet_step(MD_KICK_DRIFT) at
  * the start of step n + 1 (Sec. 1.5), saving its pass over the atoms.  pos_out
  * (double4 [n], device) must not be pos: other atoms still read pos in the same
  * pass; the caller swaps the two buffers after the call.  Velocities are left at
- * the half step n + 1/2; the record of step n holds the kinetic energy at v(n). */
+ * the half step n + 1/2; the record of step n holds the kinetic energy at v(n).
+ * The force pass keeps one displacement slot per block: MD_ERR_ARG when its grid of
+ * ceil(n_tiles * lanes / 16) blocks (rounded up to a multiple of 8) exceeds
+ * MD_DRIFT_MAX_BLOCKS. */
+#define MD_DRIFT_MAX_BLOCKS 32768
 typedef struct md_drift {
   double* pos_out;
   const double* pos_ref; /* [3][n] */
@@ -299,6 +295,18 @@ typedef struct md_drift {
   double half_skin;      /* < 0: no criterion */
   md_walls walls;        /* walls.enabled = 0: none */
 } md_drift;
+
+/* Lennard-Jones forces (eq. 1.6), energy and virial.  force is [3][n] FP64 or
+ * FP32.  If vel is not NULL the trailing half kick v += half_dt f / m is applied
+ * and the kinetic energy is reduced.  If ev is not NULL the per-box record
+ * {E, W[6], K} is written to ev[(step % ev_cap) * n_rep + rep] (step = the
+ * control block's step counter).  drift: NULL, or the next step's kick-drift to
+ * fuse (md_drift, as for md_eam_forces). */
+int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec, const double* pos,
+                 const md_nlist* nl, void* force, double* vel, double inv_mass, double half_dt,
+                 const md_drift* drift, long long* ev, int ev_cap, void* ws, void* ctl,
+                 void* stream);
+
 
 /* EAM forces: a density pass (rhobar_i = sum_j rho(r_ij), F(rhobar_i),
  * F'(rhobar_i), the energy) then a force pass

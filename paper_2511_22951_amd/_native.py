@@ -17,6 +17,7 @@ MD_TILE = 64
 MD_NN_IMG = 1 << 30
 FLAG_NEIGH_OVERFLOW, FLAG_TABLE_RANGE, FLAG_WALL, FLAG_NONFINITE, FLAG_STALE_LIST = 1, 2, 4, 8, 16
 MD_ERR_ARG = -1
+MD_DRIFT_MAX_BLOCKS = 32768
 MD_ERR_STALE_LIST = -9
 
 
@@ -117,8 +118,8 @@ _SIGS = {
     "md_eam_prepare": (_i, [_P(EAM), _i, _vp, _vp]),
     "md_bin_cells": (_i, [_P(Batch), _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "md_build_neighbors": (_i, [_P(Batch), _i, _vp, _vp, _P(NList), _vp, _vp]),
-    "md_lj_forces": (_i, [_P(Batch), _P(LJ), _i, _vp, _P(NList), _vp, _vp, _d, _d, _vp, _i, _vp,
-                          _vp, _vp]),
+    "md_lj_forces": (_i, [_P(Batch), _P(LJ), _i, _vp, _P(NList), _vp, _vp, _d, _d, _P(Drift),
+                          _vp, _i, _vp, _vp, _vp]),
     "md_eam_forces": (_i, [_P(Batch), _P(EAM), _i, _vp, _vp, _P(NList), _vp, _vp, _vp, _d, _d,
                            _P(Drift), _vp, _i, _vp, _vp, _vp]),
     "md_verlet_step": (_i, [_P(Batch), _i, _d, _vp, _vp, _vp, _i, _d, _P(Walls), _P(Langevin),

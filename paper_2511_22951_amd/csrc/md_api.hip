@@ -134,7 +134,7 @@ __global__ void k_ctl_init(md_ctl_dev* ctl) {
     ctl->thr2 = -1.0;
     ctl->pad2 = 0.0;
   }
-  for (int k = threadIdx.x; k < MD_MAX_ATOM_BLOCKS; k += blockDim.x) ctl->dmax[k] = 0.0;
+  for (int k = threadIdx.x; k < MD_DMAX_SLOTS; k += blockDim.x) ctl->dmax[k] = 0.0;
 }
 
 __global__ void k_ctl_clear_flags(md_ctl_dev* ctl) {

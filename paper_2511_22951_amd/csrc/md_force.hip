@@ -445,6 +445,38 @@ struct DriftArgs {
   md_walls_dev w;
 };
 
+// Epilogue of a force pass with the next kick-drift fused in: write the force, apply
+// the trailing half kick of this step (its kinetic energy is returned), then the next
+// step's half kick and drift with the walls at (step + 1) dt -- the same operations, in
+// the same order, as md_verlet_step(MD_KICK_DRIFT) -- into dr.pos_out; d2max gets the
+// atom's displacement from x_ref.
+template <typename R>
+__device__ __forceinline__ double fused_kick_drift(int i, int n, R fx, R fy, R fz, R* force,
+                                                   double* vel, double inv_mass, double half_dt,
+                                                   const double4* pos, const DriftArgs& dr,
+                                                   int step, double& d2max, int& bad) {
+  force[i] = fx;
+  force[n + i] = fy;
+  force[2 * n + i] = fz;
+  const double c = half_dt * inv_mass * MD_ACCEL;
+  const double F[3] = {(double)fx, (double)fy, (double)fz};
+  double v[3] = {vel[i] + c * F[0], vel[n + i] + c * F[1], vel[2 * n + i] + c * F[2]};
+  const double ke = 0.5 / (inv_mass * MD_ACCEL) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  v[0] = v[0] + c * F[0];
+  v[1] = v[1] + c * F[1];
+  v[2] = v[2] + c * F[2];
+  const double4 p = pos[i];
+  double x[3] = {p.x, p.y, p.z};
+  md_drift_atom(x, v, dr.dt, dr.w, (double)(step + 1) * dr.dt);
+  vel[i] = v[0];
+  vel[n + i] = v[1];
+  vel[2 * n + i] = v[2];
+  dr.pos_out[i] = make_double4(x[0], x[1], x[2], p.w);
+  if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) bad |= MD_FLAG_NONFINITE;
+  d2max = md_disp2(x, dr.pos_ref, i, n);
+  return ke;
+}
+
 template <typename R, int LANES, bool EV, bool TLDS, typename E>
 __device__ __forceinline__ void eam_force_body(
     const md_batch& b, const double4* __restrict__ pos, const int* __restrict__ neigh,
@@ -537,28 +569,8 @@ __device__ __forceinline__ void eam_force_body(
   int bad = 0;
   if (i >= 0 && S.l == 0) {
     if (dr.pos_out) {
-      // trailing half kick of this step (kinetic energy from it), then the next
-      // step's kick and drift, the same operations as md_verlet_step(MD_KICK_DRIFT)
-      const int n = b.n_atoms;
-      force[i] = fx;
-      force[n + i] = fy;
-      force[2 * n + i] = fz;
-      const double c = half_dt * inv_mass * MD_ACCEL;
-      const double F[3] = {(double)fx, (double)fy, (double)fz};
-      double v[3] = {vel[i] + c * F[0], vel[n + i] + c * F[1], vel[2 * n + i] + c * F[2]};
-      acc[6] = 0.5 / (inv_mass * MD_ACCEL) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-      v[0] = v[0] + c * F[0];
-      v[1] = v[1] + c * F[1];
-      v[2] = v[2] + c * F[2];
-      const double4 p = pos[i];
-      double x[3] = {p.x, p.y, p.z};
-      md_drift_atom(x, v, dr.dt, dr.w, (double)(ctl->step + 1) * dr.dt);
-      vel[i] = v[0];
-      vel[n + i] = v[1];
-      vel[2 * n + i] = v[2];
-      dr.pos_out[i] = make_double4(x[0], x[1], x[2], p.w);
-      if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) bad |= MD_FLAG_NONFINITE;
-      d2max = md_disp2(x, dr.pos_ref, i, n);
+      acc[6] = fused_kick_drift<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt, pos,
+                                   dr, ctl->step, d2max, bad);
     } else {
       acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
     }
@@ -613,11 +625,14 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_force_f64(MD_EAM_FORCE_ARGS(doub
 }
 #undef MD_EAM_FORCE_ARGS
 
-// Zero the record slot of the step being evaluated, ahead of the LJ pass whose
-// blocks add into it.
-__global__ __launch_bounds__(64) void k_ev_zero(md_batch b, long long* ev, int ev_cap,
-                                                const md_ctl_dev* ctl) {
-  zero_record(b, ev, ev_cap, ctl->step_next);
+// Ahead of the LJ pass (one block): verify the list and advance the step counter
+// (md_step_bookkeeping), and zero the record slot its blocks add into.  Doing this in
+// a kernel of its own keeps the step counter and the displacement maxima fixed while
+// the LJ pass runs (its fused kick-drift publishes new maxima).
+__global__ __launch_bounds__(256) void k_lj_prologue(md_batch b, long long* ev, int ev_cap,
+                                                     md_ctl_dev* ctl) {
+  md_step_bookkeeping(ctl);
+  if (ev) zero_record(b, ev, ev_cap, ctl->step_next);
 }
 
 // ---------------------------------------------------------------------------
@@ -631,11 +646,10 @@ template <typename R, int LANES, bool EV, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_lj(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, LJc c, R rc2, R* force, double* vel,
-    double inv_mass, double half_dt, long long* ev, int ev_cap, md_ctl_dev* ctl) {
+    double inv_mass, double half_dt, DriftArgs dr, long long* ev, int ev_cap, md_ctl_dev* ctl) {
   constexpr int U = 4;
   __shared__ double sh[MD_EV_LEN * 16];
   __shared__ double tsum[MD_EV_LEN * 16];
-  step_bookkeeping(ctl);
   const Slot S = force_slot<LANES>(b.n_tiles);
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // E, W xx yy zz xy xz yz, K
   const R sig2 = (R)c.sig2, eps4 = (R)c.eps4, eps24 = (R)c.eps24, ucut = (R)c.ucut;
@@ -693,8 +707,15 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
   fx = md_group_sum<LANES>(fx);
   fy = md_group_sum<LANES>(fy);
   fz = md_group_sum<LANES>(fz);
-  if (i >= 0 && S.l == 0)
-    acc[7] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
+  double d2max = 0.0;
+  int bad = 0;
+  if (i >= 0 && S.l == 0) {
+    if (dr.pos_out)
+      acc[7] = fused_kick_drift<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt, pos,
+                                   dr, ctl->step, d2max, bad);
+    else
+      acc[7] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
+  }
   if (EV) {
     acc[0] = 0.5 * (double)e;
 #pragma unroll
@@ -706,10 +727,10 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
     const int lb = md_remap_block(nlb);
     if (md_group_waves_sum<8>(acc, LANES, sh, res, gg, kk)) tsum[gg * MD_EV_LEN + kk] = res;
     __syncthreads();
-    // step_next: block 0 advances ctl->step while the other blocks run
     accumulate_record<TPB>(b, lb, nlb, tsum,
-                           ev + (size_t)(ctl->step_next % ev_cap) * b.n_rep * MD_EV_LEN);
+                           ev + (size_t)(ctl->step % ev_cap) * b.n_rep * MD_EV_LEN);
   }
+  if (dr.pos_out) md_publish_dmax(d2max, bad, dr.thr2, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -804,8 +825,8 @@ void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_ta
 
 template <typename R, int LANES>
 void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nlist& nl,
-               void* force, double* vel, double inv_mass, double half_dt, long long* ev, int ev_cap,
-               md_ctl_dev* ctl, hipStream_t st) {
+               void* force, double* vel, double inv_mass, double half_dt, const DriftArgs& dr,
+               long long* ev, int ev_cap, md_ctl_dev* ctl, hipStream_t st) {
   LJc c;
   c.sig2 = p.sigma * p.sigma;
   c.eps4 = 4.0 * p.eps;
@@ -820,9 +841,9 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
 #define MD_LJ_LAUNCH(EVB, E_)                                                                  \
   MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, EVB, E_>), grid, block, 0, st, b,             \
                   (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,      \
-                  inv_mass, half_dt, ev, ev_cap, ctl)
+                  inv_mass, half_dt, dr, ev, ev_cap, ctl)
+  hipLaunchKernelGGL(k_lj_prologue, dim3(1), dim3(256), 0, st, b, ev, ev_cap, ctl);
   if (ev) {
-    hipLaunchKernelGGL(k_ev_zero, dim3(1), dim3(64), 0, st, b, ev, ev_cap, ctl);
     if (big) MD_LJ_LAUNCH(true, uint64_t);
     else MD_LJ_LAUNCH(true, uint32_t);
   } else {
@@ -843,6 +864,25 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
     default: { constexpr int L_ = 16; CALL; } break; \
   }
 
+// The fused kick-drift's arguments (shared by the EAM and LJ passes); the force pass
+// grid must fit the control block's displacement slots.
+static int drift_load(const md_batch* b, const md_nlist* nl, const double* pos, double* vel,
+                      double half_dt, const md_drift* drift, DriftArgs* dr) {
+  *dr = DriftArgs{nullptr, nullptr, 0.0, -1.0, md_walls_dev{0, 2, 0.0, 0.0, 0.0}};
+  if (!drift) return MD_OK;
+  if (!vel || !(half_dt > 0.0) || !drift->pos_out || !drift->pos_ref ||
+      drift->pos_out == pos || !isfinite(drift->dt) || half_dt != 0.5 * drift->dt)
+    return MD_ERR_ARG;
+  if (md_walls_load(&drift->walls, &dr->w) != MD_OK) return MD_ERR_ARG;
+  dr->pos_out = (double4*)drift->pos_out;
+  dr->pos_ref = drift->pos_ref;
+  dr->dt = drift->dt;
+  dr->thr2 = drift->half_skin < 0.0 ? -1.0 : drift->half_skin * drift->half_skin;
+  const int tpb = FBLOCK / (64 * nl->lanes);
+  if (md_grid_blocks((b->n_tiles + tpb - 1) / tpb) > MD_DMAX_SLOTS) return MD_ERR_ARG;
+  return MD_OK;
+}
+
 extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec,
                              const void* table, const double* pos, const md_nlist* nl,
                              void* force, double* saved, double* vel, double inv_mass,
@@ -855,20 +895,8 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   if (vel && !(inv_mass > 0.0)) return MD_ERR_ARG;
   // FP32 takes 1-8 lanes per atom (16 is not supported)
   if (prec == MD_FP32 && nl->lanes > 8) return MD_ERR_ARG;
-  DriftArgs dr{nullptr, nullptr, 0.0, -1.0, md_walls_dev{0, 2, 0.0, 0.0, 0.0}};
-  if (drift) {
-    if (!vel || !(half_dt > 0.0) || !drift->pos_out || !drift->pos_ref ||
-        drift->pos_out == pos || !isfinite(drift->dt) || half_dt != 0.5 * drift->dt)
-      return MD_ERR_ARG;
-    if (md_walls_load(&drift->walls, &dr.w) != MD_OK) return MD_ERR_ARG;
-    dr.pos_out = (double4*)drift->pos_out;
-    dr.pos_ref = drift->pos_ref;
-    dr.dt = drift->dt;
-    dr.thr2 = drift->half_skin < 0.0 ? -1.0 : drift->half_skin * drift->half_skin;
-    // one displacement slot per block of the force pass
-    const int tpb = FBLOCK / (64 * nl->lanes);
-    if (md_grid_blocks((b->n_tiles + tpb - 1) / tpb) > MD_MAX_ATOM_BLOCKS) return MD_ERR_ARG;
-  }
+  DriftArgs dr;
+  if (drift_load(b, nl, pos, vel, half_dt, drift, &dr) != MD_OK) return MD_ERR_ARG;
   if (b->n_atoms == 0 || b->n_tiles == 0) return MD_OK;
   const md_table_layout TL = md_table_plan(p, prec);
   const md_ws_layout WL = md_ws_plan(b);
@@ -890,22 +918,26 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
 
 extern "C" int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec,
                             const double* pos, const md_nlist* nl, void* force, double* vel,
-                            double inv_mass, double half_dt, long long* ev, int ev_cap, void* ws,
-                            void* ctl, void* stream) {
+                            double inv_mass, double half_dt, const md_drift* drift, long long* ev,
+                            int ev_cap, void* ws, void* ctl, void* stream) {
   if (!batch_ok(b) || !p || !pos || !nlist_ok(nl) || !force || !ws || !ctl) return MD_ERR_ARG;
   if (!(p->sigma > 0.0) || !(p->r_cut > 0.0)) return MD_ERR_ARG;
   if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
   if (ev && ev_cap < 1) return MD_ERR_ARG;
   if (vel && !(inv_mass > 0.0)) return MD_ERR_ARG;
+  DriftArgs dr;
+  if (drift_load(b, nl, pos, vel, half_dt, drift, &dr) != MD_OK) return MD_ERR_ARG;
   if (b->n_atoms == 0 || b->n_tiles == 0) return MD_OK;
   hipStream_t st = (hipStream_t)stream;
   md_ctl_dev* c = (md_ctl_dev*)ctl;
   if (prec == MD_FP32) {
     MD_DISPATCH_LANES(nl->lanes, (launch_lj<float, L_>(*b, *p, pos, *nl, force, vel, inv_mass,
-                                                       half_dt, (long long*)ev, ev_cap, c, st)));
+                                                       half_dt, dr, (long long*)ev, ev_cap, c,
+                                                       st)));
   } else {
     MD_DISPATCH_LANES(nl->lanes, (launch_lj<double, L_>(*b, *p, pos, *nl, force, vel, inv_mass,
-                                                        half_dt, (long long*)ev, ev_cap, c, st)));
+                                                        half_dt, dr, (long long*)ev, ev_cap, c,
+                                                        st)));
   }
   MD_LAUNCH_CHECK();
   return MD_OK;

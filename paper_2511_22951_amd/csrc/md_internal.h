@@ -18,6 +18,7 @@
 
 // Device control block (md_ctl_bytes()).
 #define MD_MAX_ATOM_BLOCKS 4096  // grid cap of the per-atom kernels (grid-stride beyond)
+#define MD_DMAX_SLOTS MD_DRIFT_MAX_BLOCKS  // per-block displacement maxima a drifting kernel may publish
 
 struct md_ctl_dev {
   int rebuild;     // 1: the MD_IF_FLAGGED rebuild kernels do their work
@@ -30,7 +31,7 @@ struct md_ctl_dev {
   int pad;
   double thr2;     // (half skin)^2 of the last kick-drift; < 0: no criterion
   double pad2;
-  double dmax[MD_MAX_ATOM_BLOCKS];  // per-block max |x - x_ref|^2 of the last drift
+  double dmax[MD_DMAX_SLOTS];  // per-block max |x - x_ref|^2 of the last drift
 };
 
 // Largest per-block displacement of the last drift above the threshold?  Read

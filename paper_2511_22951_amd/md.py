@@ -269,16 +269,17 @@ def md_build_neighbors(st: State, nl: NeighborList, mode=N.MD_ALWAYS, stream=Non
 
 
 def md_lj_forces(st: State, p, nl: NeighborList, inv_mass=0.0, half_dt=0.0, kick=False,
-                 ev=None, ev_cap=1, stream=None):
+                 ev=None, ev_cap=1, drift=None, stream=None):
     vel = st.vel if kick else None
     check(N.lib().md_lj_forces(C.byref(st.plan.c), C.byref(p), st.precision, _ptr(st.pos),
                                C.byref(nl.c), _ptr(st.force), _ptr(vel), float(inv_mass),
-                               float(half_dt), _ptr(ev), int(ev_cap), _ptr(st.ws), _ptr(st.ctl),
+                               float(half_dt), C.byref(drift) if drift is not None else None,
+                               _ptr(ev), int(ev_cap), _ptr(st.ws), _ptr(st.ctl),
                                _stream(stream)), "md_lj_forces")
 
 
 def drift_params(pos_out, pos_ref, dt, half_skin, walls=None):
-    """md_drift: the next step's kick-drift to fuse into md_eam_forces."""
+    """md_drift: the next step's kick-drift to fuse into md_lj_forces or md_eam_forces."""
     w = walls_params(walls) if isinstance(walls, dict) else walls
     return N.Drift(_ptr(pos_out), _ptr(pos_ref), float(dt), float(half_skin),
                    w if w is not None else N.Walls(0, 2, 0.0, 0.0, 0.0))

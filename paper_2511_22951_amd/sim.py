@@ -7,7 +7,7 @@ One step, all on one stream, no host synchronisation:
   md_bin_cells, md_build_neighbors    rebuild (policy below)
   md_eam_forces / md_lj_forces        forces, energy, virial, trailing kick v += dt/2 f/m
 
-With fused=True (EAM) the force pass also performs the next step's kick-drift
+With fused=True (EAM or LJ) the force pass also performs the next step's kick-drift
 (md_drift), writing the new positions into a second buffer that becomes current
 after the call, so from the second step on a step is rebuild + density + force.
 The arithmetic is the same, bit for bit; between steps the state is then one
@@ -37,12 +37,21 @@ from . import _native as N
 from . import md
 
 
+def fused_grid_fits(n_tiles, lanes):
+    """Whether a force pass of `lanes` lanes per atom over n_tiles tiles (16 / lanes tiles per
+    1024-thread block, the grid rounded up to a multiple of 8) fits the displacement slots
+    the fused kick-drift publishes into."""
+    tpb = 16 // lanes
+    blocks = (n_tiles + tpb - 1) // tpb
+    return (blocks + 7) // 8 * 8 <= N.MD_DRIFT_MAX_BLOCKS
+
+
 class Simulation:
     def __init__(self, system, precision=N.MD_FP64, lanes=4, max_neigh=128, ev_cap=1024,
                  device="cuda", table=None, rebuild_every=0, fused=False, thermostat=None):
         self.sys = system
         # the Langevin update runs in the kick-drift kernel, so it is not fused
-        self.fused = bool(fused) and system.potential == "eam" and thermostat is None
+        self.fused = bool(fused) and system.potential in ("eam", "lj") and thermostat is None
         self.primed = False  # fused: the last force pass already did the next kick-drift
         self.pos_alt = None
         self.rebuild_every = int(rebuild_every)
@@ -58,6 +67,10 @@ class Simulation:
         self.plan = md.Plan([system.box], [system.pos.shape[0]], self.r_ns, device)
         self.state = md.State(self.plan, system.pos, system.vel, precision)
         self.nl = md.NeighborList(self.plan.n_atoms, max_neigh, lanes, device)
+        if self.fused and not fused_grid_fits(self.plan.n_tiles, lanes):
+            raise ValueError("fused kick-drift: %d lanes per atom over %d atoms exceed the "
+                             "force pass's %d displacement slots; use fewer lanes or fused=False"
+                             % (lanes, self.plan.n_atoms, N.MD_DRIFT_MAX_BLOCKS))
         self.inv_mass = 1.0 / system.mass
         self.dt = system.dt_ps
         self.half_skin = 0.5 * system.skin
@@ -134,9 +147,13 @@ class Simulation:
                 self.pos_alt = torch.empty_like(st.pos)
             drift = md.drift_params(self.pos_alt, st.pos_ref, self.dt, self.half_skin,
                                     self.walls)
-            md.md_eam_forces(st, self.pot, self.nl, self.table, None, self.inv_mass,
-                             0.5 * self.dt, kick=True, ev=self.ev if ev else None,
-                             ev_cap=self.ev_cap, drift=drift)
+            if self.pot is None:
+                md.md_lj_forces(st, self.lj, self.nl, self.inv_mass, 0.5 * self.dt, kick=True,
+                                ev=self.ev if ev else None, ev_cap=self.ev_cap, drift=drift)
+            else:
+                md.md_eam_forces(st, self.pot, self.nl, self.table, None, self.inv_mass,
+                                 0.5 * self.dt, kick=True, ev=self.ev if ev else None,
+                                 ev_cap=self.ev_cap, drift=drift)
             st.pos, self.pos_alt = self.pos_alt, st.pos
             self.primed = True
         else:

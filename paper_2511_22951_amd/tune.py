@@ -79,7 +79,7 @@ def best_lanes(system, prec, candidates=CANDIDATES, samples=10, use_cache=True):
         if key is None:
             mean_nb = sim.nl.lengths().double().mean().item()
             key = _key(name, system.potential, prec, sim.plan.n_atoms, mean_nb)
-            if key in cache:
+            if key in cache and int(cache[key]["lanes"]) in candidates:
                 return int(cache[key]["lanes"])
         t = time_kernels(sim, kernels, samples)
         results[lanes] = sum(t.values())

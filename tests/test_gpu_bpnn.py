@@ -112,3 +112,33 @@ def test_bpnn_rejects_malformed_parameters():
     bad.weights = None
     assert call(bad) == N.MD_ERR_ARG
     st.check_flags()
+
+
+def test_bpnn_batch_equals_single_boxes():
+    """Two boxes of different size in one batch give each box's own forces and records."""
+    import torch
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd import md
+    p = mi.bpnn_params()
+    pot = md.BPNNPotential(p)
+    systems = [mi.bpnn_copper(cells=4, seed=11), mi.bpnn_copper(cells=5, seed=12)]
+    r_ns = p["r_cut"] + 0.3
+
+    def run(sys_list):
+        plan = md.Plan([s.box for s in sys_list], [s.pos.shape[0] for s in sys_list], r_ns)
+        st = md.State(plan, np.concatenate([s.pos for s in sys_list]), None, N.MD_FP64)
+        nl = md.NeighborList(plan.n_atoms, 128, 4)
+        md.md_bin_cells(st)
+        md.md_build_neighbors(st, nl)
+        ev = md.ev_buffer(1, len(sys_list))
+        md.md_bpnn_forces(st, pot, nl, ev=ev, ev_cap=1)
+        st.check_flags()
+        return st.forces(), md.ev_values(ev)[0]
+
+    fb, eb = run(systems)
+    n0 = systems[0].pos.shape[0]
+    for k, s in enumerate(systems):
+        f1, e1 = run([s])
+        part = fb[:n0] if k == 0 else fb[n0:]
+        assert np.abs(part - f1).max() <= 1e-13 * np.abs(f1).max()
+        assert np.allclose(eb[k], e1[0], rtol=1e-12, atol=1e-9)

@@ -88,8 +88,9 @@ def test_al640k_shock_configuration():
 
 def test_lj13m_paper_configuration():
     """The LJ test of Sec. 1.7 at its size: 12,967,168 Ar atoms, lists rebuilt every 10
-    steps (the list holds over 2^30 entries, so the passes take 64-bit entry offsets);
-    FP64 and FP32-mixed, 20 steps with 10-step graphs."""
+    steps (the list holds over 2^30 entries, so the passes take 64-bit entry offsets), the
+    next kick-drift fused into the LJ pass; FP64 and FP32-mixed, 20 steps with 10-step
+    graphs."""
     from paper_2511_22951_amd import _native as N
     from paper_2511_22951_amd.sim import Simulation
     s = mi.lj_argon_benchmark()
@@ -97,12 +98,12 @@ def test_lj13m_paper_configuration():
     sample = np.random.default_rng(2026).choice(n, 128, replace=False)
     for prec, tol, tol_net in ((N.MD_FP64, 1e-11, 1e-10), (N.MD_FP32, 1e-5, 1e-5)):
         sim = Simulation(s, precision=prec, lanes=2, max_neigh=112, ev_cap=64,
-                         rebuild_every=10).setup()
+                         rebuild_every=10, fused=True).setup()
         assert sim.nl.max_neigh * sim.nl.npad >= 1 << 30
         n0 = sim.state.check_flags()["n_rebuilds"]
         sim.run(20, graph_steps=10)
         assert sim.state.check_flags()["n_rebuilds"] - n0 == 2
-        x = sim.state.positions()
+        x = sim.previous_positions()  # the positions the last force pass saw
         f = sim.state.forces()
         lj = s.lj
         r = core.lj_sampled(x, s.box, lj.eps, lj.sigma, lj.r_cut, sample)

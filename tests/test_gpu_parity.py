@@ -297,6 +297,27 @@ def test_fused_kick_drift_equals_separate(mdmod, prec, policy):
     assert np.array_equal(a.state.velocities(), b.state.velocities())
 
 
+@pytest.mark.parametrize("prec,policy", [(0, 0), (1, 5)])
+def test_fused_kick_drift_lj_equals_separate(mdmod, prec, policy):
+    """The same for the LJ pass: argon 4^3 cells (256 atoms) at 300 K, 30 steps."""
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.lj_argon(cells=4)
+    s.vel = s.vel * np.sqrt(3.0)
+    a = Simulation(s, precision=prec, lanes=2, rebuild_every=policy).setup()
+    b = Simulation(s, precision=prec, lanes=2, rebuild_every=policy, fused=True).setup()
+    assert b.fused
+    a.run(30, graph_steps=10 if policy else 0)
+    b.run(30, graph_steps=10 if policy else 0)
+    ia, ib = a.state.check_flags(), b.state.check_flags()
+    assert ia["n_rebuilds"] == ib["n_rebuilds"]
+    assert np.array_equal(b.previous_positions(), a.state.positions())
+    assert np.array_equal(a.energies(range(31)), b.energies(range(31)))
+    mdmod.md_verlet_step(a.state, N.MD_KICK_DRIFT, a.dt, a.inv_mass, a.walls, a.half_skin)
+    assert np.array_equal(a.state.positions(), b.state.positions())
+    assert np.array_equal(a.state.velocities(), b.state.velocities())
+
+
 def test_fused_kick_drift_with_walls(mdmod):
     """Fused kick-drift with the piston and top wall (the shock set-up) equals the separate
     one bit for bit."""
