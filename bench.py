@@ -438,6 +438,24 @@ def bench_al_shock(args):
                         "profiles_257_slabs": 1e3 * prof_ms},
         "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        from oracle import core, profiles
+        o = np.argsort(sim.state.id.cpu().numpy(), kind="stable")
+        x, v = sim.state.positions(), sim.state.velocities()
+        sample = np.random.default_rng(5).choice(n, 64, replace=False)
+        t0 = time.perf_counter()
+        core.eam_sampled(x, system.box, core.EAMPotential.from_table(system.table), sample)
+        t_f = time.perf_counter() - t0
+        e_h, w_h = obs["e"].cpu().numpy()[o], obs["w"].cpu().numpy().T[o]
+        t0 = time.perf_counter()
+        profiles.profiles(x, v, system.mass, e_h, w_h, system.box, 2, 0.0, lz / nb, nb)
+        t_p = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": len(sample) / t_f, "unit": "atom-steps/s (forces only)",
+            "cores": core.num_threads(), "kind": "oracle",
+            "sample": "FP64 O(N) EAM force sums of %d sampled atoms over all %d atoms, %.1f s; "
+                      "the oracle's 257 slab profiles of the same state took %.2f s"
+                      % (len(sample), n, t_f, t_p)}
     print(json.dumps(out), flush=True)
 
 
@@ -588,6 +606,24 @@ def bench_nvt(args):
         "paths": res,
         "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        from oracle import core, thermostat
+        sample = np.random.default_rng(6).choice(n, 64, replace=False)
+        t0 = time.perf_counter()
+        core.eam_sampled(system.pos, system.box, core.EAMPotential.from_table(system.table),
+                         sample)
+        t_f = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        thermostat.o_step(system.pos, system.vel, np.arange(n), 1, lang, system.mass,
+                          system.dt_ps)
+        t_o = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": len(sample) / (t_f + t_o * len(sample) / n),
+            "unit": "atom-steps/s (forces and Langevin update)", "cores": core.num_threads(),
+            "kind": "oracle",
+            "sample": "FP64 O(N) EAM force sums of %d sampled atoms (%.1f s) plus their share of "
+                      "the oracle's Langevin update of all %d atoms (%.2f s in all)"
+                      % (len(sample), t_f, n, t_o)}
     print(json.dumps(out), flush=True)
 
 
@@ -658,6 +694,17 @@ def bench_bpnn(args):
         "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"],
         "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        from oracle import bpnn, core
+        small = mi.bpnn_copper(cells=4)
+        t0 = time.perf_counter()
+        bpnn.forces(small.pos, small.box, small.extra["bpnn"])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": small.pos.shape[0] / dt, "unit": "atom-steps/s (energy and forces)",
+            "cores": 1, "kind": "oracle",
+            "sample": "energy and forces of the 256-atom Cu box (4^3 cells, same potential) by "
+                      "the numpy oracle, %.1f s" % dt}
     print(json.dumps(out), flush=True)
 
 
