@@ -629,7 +629,7 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_force_f64(MD_EAM_FORCE_ARGS(doub
 // (md_step_bookkeeping), and zero the record slot its blocks add into.  Doing this in
 // a kernel of its own keeps the step counter and the displacement maxima fixed while
 // the LJ pass runs (its fused kick-drift publishes new maxima).
-__global__ __launch_bounds__(256) void k_lj_prologue(md_batch b, long long* ev, int ev_cap,
+__global__ __launch_bounds__(1024) void k_lj_prologue(md_batch b, long long* ev, int ev_cap,
                                                      md_ctl_dev* ctl) {
   md_step_bookkeeping(ctl);
   if (ev) zero_record(b, ev, ev_cap, ctl->step_next);
@@ -842,7 +842,7 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
   MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, EVB, E_>), grid, block, 0, st, b,             \
                   (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,      \
                   inv_mass, half_dt, dr, ev, ev_cap, ctl)
-  hipLaunchKernelGGL(k_lj_prologue, dim3(1), dim3(256), 0, st, b, ev, ev_cap, ctl);
+  hipLaunchKernelGGL(k_lj_prologue, dim3(1), dim3(1024), 0, st, b, ev, ev_cap, ctl);
   if (ev) {
     if (big) MD_LJ_LAUNCH(true, uint64_t);
     else MD_LJ_LAUNCH(true, uint32_t);
