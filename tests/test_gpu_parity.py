@@ -348,3 +348,22 @@ def test_stale_list_is_detected(mdmod):
     with pytest.raises(mdmod.MDError) as e:
         sim.state.check_flags()
     assert e.value.status == -9
+
+
+@pytest.mark.parametrize("pot,prec", [("eam", 1), ("eam", 0), ("lj", 1)])
+def test_big_list_offsets_equal_small_list(mdmod, pot, prec):
+    """A list of 2^30 entries (4 GiB: 2048 atoms with room for 524,288 neighbours each) takes
+    the 64-bit entry offsets of the force passes and the 64-bit addressing of the list build;
+    forces and records equal those of an ordinary list bit for bit."""
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.eam_copper(cells=8) if pot == "eam" else mi.lj_argon(cells=8)
+    out = []
+    for max_neigh in (128, 524288):
+        sim = Simulation(s, precision=prec, lanes=2, max_neigh=max_neigh, ev_cap=8).setup()
+        assert (sim.nl.max_neigh * sim.nl.npad >= 1 << 30) == (max_neigh > 128)
+        sim.run(3)
+        info = sim.state.check_flags()
+        out.append((sim.state.forces(), sim.energies([info["step"]])[0]))
+        del sim
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
