@@ -27,6 +27,10 @@
  *     carries the caller's original atom ids along with the permutation.
  *     Positions are wrapped into the box at that point only; between rebuilds
  *     an atom may stand outside its periodic box by at most half the skin.
+ *   - A batch may hold no atoms (n_atoms = 0, n_tiles = 0, tiles may then be
+ *     NULL; a box of a batch may be empty too).  With n_atoms = 0 every entry
+ *     point checks its arguments and returns MD_OK without enqueuing work, except
+ *     md_profiles and md_eam_backward, which still write their (zero) results.
  *   - Return values are md_status codes.  Argument errors return at once and
  *     enqueue nothing.  Conditions detected on the device set sticky bits in
  *     the control block; md_read_flags() reads and maps them.

@@ -181,7 +181,7 @@ extern "C" int md_eam_backward(const md_batch* b, const md_eam* p, md_precision 
                                const double* pos, const md_nlist* nl, const double* saved,
                                const double* grad_force, double* grad_coef, void* ws, void* ctl,
                                void* stream) {
-  if (!b || b->n_rep < 1 || !b->tiles || !b->domains || b->tile_atoms != MD_TILE) return MD_ERR_ARG;
+  if (!md_batch_ok(b)) return MD_ERR_ARG;
   if (!adj_ok(p) || !pos || !nl || !nl->neigh || !nl->nneigh || !saved || !grad_force ||
       !grad_coef || !ws || !ctl)
     return MD_ERR_ARG;

@@ -503,7 +503,7 @@ extern "C" int md_bpnn_forces(const md_batch* b, const md_bpnn* p, const double*
                               const md_nlist* nl, double* force, double* e_atom, double* vel,
                               double inv_mass, double half_dt, long long* ev, int ev_cap,
                               void* ws, void* ctl, void* stream) {
-  if (!b || b->n_rep < 1 || !b->tiles || !b->domains || b->tile_atoms != MD_TILE) return MD_ERR_ARG;
+  if (!md_batch_ok(b)) return MD_ERR_ARG;
   if (!pos || !nl || !nl->neigh || !nl->nneigh || !force || !ws || !ctl) return MD_ERR_ARG;
   if (nl->lanes < 1 || nl->lanes > MD_MAX_LANES || nl->max_neigh < nl->lanes) return MD_ERR_ARG;
   if (ev && ev_cap < 1) return MD_ERR_ARG;

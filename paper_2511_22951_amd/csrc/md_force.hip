@@ -736,12 +736,6 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
 // ---------------------------------------------------------------------------
 // host dispatch
 // ---------------------------------------------------------------------------
-bool batch_ok(const md_batch* b) {
-  return b && b->n_rep >= 1 && b->n_atoms >= 0 && b->n_atoms <= MD_MAX_ATOMS &&
-         b->n_tiles >= 0 && b->n_cells >= 1 &&
-         b->tile_atoms == MD_TILE && b->domains && (b->tiles || b->n_tiles == 0);
-}
-
 bool nlist_ok(const md_nlist* nl) {
   if (!nl || !nl->neigh || !nl->nneigh) return false;
   const int L = nl->lanes;
@@ -888,7 +882,7 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
                              void* force, double* saved, double* vel, double inv_mass,
                              double half_dt, const md_drift* drift, long long* ev, int ev_cap,
                              void* ws, void* ctl, void* stream) {
-  if (!batch_ok(b) || !md_eam_ok(p) || !table || !pos || !nlist_ok(nl) || !force || !ws || !ctl)
+  if (!md_batch_ok(b) || !md_eam_ok(p) || !table || !pos || !nlist_ok(nl) || !force || !ws || !ctl)
     return MD_ERR_ARG;
   if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
   if (ev && ev_cap < 1) return MD_ERR_ARG;
@@ -920,7 +914,7 @@ extern "C" int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec
                             const double* pos, const md_nlist* nl, void* force, double* vel,
                             double inv_mass, double half_dt, const md_drift* drift, long long* ev,
                             int ev_cap, void* ws, void* ctl, void* stream) {
-  if (!batch_ok(b) || !p || !pos || !nlist_ok(nl) || !force || !ws || !ctl) return MD_ERR_ARG;
+  if (!md_batch_ok(b) || !p || !pos || !nlist_ok(nl) || !force || !ws || !ctl) return MD_ERR_ARG;
   if (!(p->sigma > 0.0) || !(p->r_cut > 0.0)) return MD_ERR_ARG;
   if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
   if (ev && ev_cap < 1) return MD_ERR_ARG;

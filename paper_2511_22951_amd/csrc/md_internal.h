@@ -70,6 +70,14 @@ struct md_ws_layout {
 
 static inline size_t md_align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// A well-formed batch descriptor (host check of every entry point).  A batch may hold
+// no atoms; its tile array may then be NULL.
+static inline bool md_batch_ok(const md_batch* b) {
+  return b && b->n_rep >= 1 && b->n_atoms >= 0 && b->n_atoms <= MD_MAX_ATOMS &&
+         b->n_tiles >= 0 && b->n_cells >= 1 && b->tile_atoms == MD_TILE && b->domains &&
+         (b->tiles || b->n_tiles == 0);
+}
+
 static inline md_ws_layout md_ws_plan(const md_batch* b) {
   md_ws_layout L;
   size_t n = (size_t)b->n_atoms, o = 0;

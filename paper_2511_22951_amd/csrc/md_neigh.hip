@@ -491,16 +491,10 @@ __global__ __launch_bounds__(CELL_BLOCK) void k_build(md_batch b, int mode,
 
 }  // namespace
 
-static bool batch_ok(const md_batch* b) {
-  return b && b->n_rep >= 1 && b->n_atoms >= 0 && b->n_atoms <= MD_MAX_ATOMS &&
-         b->n_tiles >= 0 && b->n_cells >= 1 &&
-         b->tile_atoms == MD_TILE && b->domains && (b->tiles || b->n_tiles == 0);
-}
-
 extern "C" int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos, double* vel,
                             int* id, double* pos_ref, int* cell_start, void* ws, void* ctl,
                             void* stream) {
-  if (!batch_ok(b) || !pos || !vel || !id || !pos_ref || !cell_start || !ws || !ctl)
+  if (!md_batch_ok(b) || !pos || !vel || !id || !pos_ref || !cell_start || !ws || !ctl)
     return MD_ERR_ARG;
   if (mode != MD_ALWAYS && mode != MD_IF_FLAGGED) return MD_ERR_ARG;
   if (b->n_atoms == 0) return MD_OK;
@@ -547,7 +541,7 @@ extern "C" int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos
 extern "C" int md_build_neighbors(const md_batch* b, md_rebuild_mode mode, const double* pos,
                                   const int* cell_start, const md_nlist* nl, void* ctl,
                                   void* stream) {
-  if (!batch_ok(b) || !pos || !cell_start || !nl || !nl->neigh || !nl->nneigh || !ctl)
+  if (!md_batch_ok(b) || !pos || !cell_start || !nl || !nl->neigh || !nl->nneigh || !ctl)
     return MD_ERR_ARG;
   if (mode != MD_ALWAYS && mode != MD_IF_FLAGGED) return MD_ERR_ARG;
   int lg = -1;

@@ -339,7 +339,7 @@ bool spline_ok(const md_spline& s) { return s.coef && s.ncoef >= 6 && s.h > 0.0;
 extern "C" int md_atom_observables(const md_batch* b, const md_eam* eam, const md_lj* lj,
                                    const double* pos, const md_nlist* nl, double* e_atom,
                                    double* w_atom, double* rho_fp, void* ctl, void* stream) {
-  if (!b || b->n_rep < 1 || !b->tiles || !b->domains || b->tile_atoms != MD_TILE) return MD_ERR_ARG;
+  if (!md_batch_ok(b)) return MD_ERR_ARG;
   if ((eam == nullptr) == (lj == nullptr)) return MD_ERR_ARG;
   if (!pos || !nl || !nl->neigh || !nl->nneigh || !e_atom || !w_atom || !ctl) return MD_ERR_ARG;
   if (nl->lanes < 1 || nl->lanes > MD_MAX_LANES || nl->max_neigh < nl->lanes) return MD_ERR_ARG;
@@ -377,7 +377,7 @@ extern "C" int md_profiles(const md_batch* b, int axis, double lo, double width,
                            const double* pos, const double* vel, double mass,
                            const double* e_atom, const double* w_atom, double* out, void* ws,
                            void* stream) {
-  if (!b || b->n_rep != 1 || !b->tiles || !b->domains || b->tile_atoms != MD_TILE) return MD_ERR_ARG;
+  if (!md_batch_ok(b) || b->n_rep != 1) return MD_ERR_ARG;
   if (axis < 0 || axis > 2 || !(width > 0.0) || !isfinite(lo) || n_bins < 1 ||
       n_bins > MD_MAX_PROFILE_BINS || !(mass > 0.0))
     return MD_ERR_ARG;

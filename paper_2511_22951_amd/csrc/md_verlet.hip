@@ -112,7 +112,7 @@ extern "C" int md_verlet_step(const md_batch* b, md_verlet_phase phase, double d
                               double* vel, const void* force, md_precision prec, double inv_mass,
                               const md_walls* walls, const md_langevin* lang,
                               const double* pos_ref, double half_skin, void* ctl, void* stream) {
-  if (!b || b->n_rep < 1 || !b->tiles || !b->domains || b->tile_atoms != MD_TILE) return MD_ERR_ARG;
+  if (!md_batch_ok(b)) return MD_ERR_ARG;
   if (!vel || !force || !(inv_mass > 0.0) || !isfinite(dt)) return MD_ERR_ARG;
   if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
   if (b->n_atoms == 0) return MD_OK;
