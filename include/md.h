@@ -96,7 +96,9 @@ typedef struct md_domain {
   int pad;
 } md_domain;
 
-/* A work tile: up to tile_atoms consecutive atoms of one box. */
+/* A work tile: up to tile_atoms consecutive atoms of one box.  The kernels take
+ * tiles of MD_TILE_ATOMS atoms (one wavefront at one lane per atom). */
+#define MD_TILE_ATOMS 64
 typedef struct md_tile {
   int rep;
   int first;
@@ -212,7 +214,8 @@ typedef struct md_langevin {
  * ------------------------------------------------------------------------- */
 
 /* Count the cells and tiles a batch needs.  Host arrays: boxes[n_rep],
- * atom_off[n_rep + 1].  Returns MD_ERR_BOX if a periodic length is not above
+ * atom_off[n_rep + 1] (atom_off[0] = 0, box r holds atoms atom_off[r] ..
+ * atom_off[r + 1] - 1); tile_atoms must be MD_TILE_ATOMS.  Returns MD_ERR_BOX if a periodic length is not above
  * 2 r_ns (the minimum image of every neighbour must be unique), MD_ERR_ARG if
  * the batch holds more than MD_MAX_ATOMS atoms (the passes address the 32-byte
  * position records with 32-bit byte offsets). */

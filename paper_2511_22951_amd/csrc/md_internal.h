@@ -8,7 +8,7 @@
 #include "md.h"
 
 #define MD_WAVE 64
-#define MD_TILE 64           // atoms per work tile (one wavefront at one lane per atom)
+#define MD_TILE MD_TILE_ATOMS  // atoms per work tile (one wavefront at one lane per atom)
 #define MD_ATOM_BLOCK 256    // threads per block of the per-atom kernels (4 tiles)
 #define MD_XCD 8             // accelerator complex dies on MI355X
 #define MD_MAX_LANES 16
