@@ -126,6 +126,25 @@ class StaleList(Exception):
         self.k = k
 
 
+def with_valid_period(run, name=""):
+    """run(k_cap) -> result dict, raising StaleList(k) when its timed run used a stale list.
+    Such a run is void: it is repeated from its initial state with the period capped at
+    k - 1 until one keeps every list valid.  result["retries"] counts the void runs."""
+    k_cap, attempt = None, 0
+    while True:
+        try:
+            result = run(k_cap)
+            break
+        except StaleList as e:
+            k_cap, attempt = e.k - 1, attempt + 1
+            if k_cap < 1:
+                raise RuntimeError("no rebuild period kept the lists valid") from e
+            print("[bench] %s: a list went stale at period %d; repeating with period %d"
+                  % (name, e.k, k_cap), file=sys.stderr, flush=True)
+    result["retries"] = attempt
+    return result
+
+
 def run_path(system, prec, lanes, args, k_cap=None):
     import torch
     from paper_2511_22951_amd import _native as N
@@ -286,20 +305,8 @@ def main():
              "fp64": [("fp64", N.MD_FP64)]}[args.precision]
     for name, prec in precs:
         lanes = args.lanes or autotune_lanes(system, prec)
-        k_cap, attempt = None, 0
-        while True:
-            try:
-                results[name] = run_path(system, prec, lanes, args, k_cap)
-                break
-            except StaleList as e:
-                # a list outlived the half-skin criterion: that run is void; repeat the
-                # path from its initial state with a shorter rebuild period
-                k_cap, attempt = e.k - 1, attempt + 1
-                if k_cap < 1:
-                    raise RuntimeError("no rebuild period kept the lists valid")
-                print("[bench] %s: a list went stale at period %d; repeating with period %d"
-                      % (name, e.k, k_cap), file=sys.stderr, flush=True)
-        results[name]["retries"] = attempt
+        results[name] = with_valid_period(
+            lambda k_cap: run_path(system, prec, lanes, args, k_cap), name)
         print("[bench] %s: %.3f ms/step, lanes %d, force kernel %.2f us" % (
             name, results[name]["ms"] / args.steps, lanes,
             1e3 * results[name]["kernels_ms"]["eam_force"][0]), file=sys.stderr, flush=True)
