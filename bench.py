@@ -2,10 +2,12 @@
 
 Workload: EAM Cu, fcc 32^3 cells = 131,072 atoms, a = 3.615 A, N(0, 0.05^2) A
 displacements, 300 K velocities, dt = 1 fs, skin 0.3 A (r_ns = 5.8 A), 2000-point
-spline tables; velocity Verlet with predicated neighbour-list rebuilds (half-skin
-displacement check), energies and virial reduced every step.  A step is the whole
-hot path: kick-drift + displacement check, (predicated) binning and list build,
-EAM density pass, EAM force pass with the trailing kick and reductions.
+spline tables; velocity Verlet with neighbour lists rebuilt every k steps, k taken from a
+warm-up on the half-skin threshold and the criterion verified on every step (a run whose
+list went stale is void and repeated with a shorter k); energies and virial reduced every
+step.  A step is the whole hot path: kick-drift + displacement check, binning and list
+build when due, EAM density pass, EAM force pass with the trailing kick and reductions
+(the next kick-drift fused into it).
 
 Two GPU paths are timed: FP32-mixed (FP32 pair arithmetic and force sums, FP64
 positions/integration/reductions) -- the headline `value` -- and plain FP64.
