@@ -53,13 +53,13 @@ def _check_forces(sim, s, sample, tol, tol_net):
 
 @pytest.mark.parametrize("prec", [1, 0])
 def test_cu131k_bench_configuration(prec):
-    """EAM Cu fcc 32^3 (131,072 atoms): 36 steps, rebuilds every 12 steps, 18-step graphs."""
+    """EAM Cu fcc 32^3 (131,072 atoms): 360 steps, rebuilds every 12 steps, 18-step graphs."""
     from paper_2511_22951_amd.sim import Simulation
     s = mi.eam_copper(cells=32)
     sim = Simulation(s, precision=prec, lanes=2, ev_cap=64, rebuild_every=12, fused=True).setup()
     n0 = sim.state.check_flags()["n_rebuilds"]
-    sim.run(36, graph_steps=18)
-    assert sim.state.check_flags()["n_rebuilds"] - n0 == 3  # steps 12, 24, 36
+    sim.run(360, graph_steps=18)
+    assert sim.state.check_flags()["n_rebuilds"] - n0 == 30  # steps 12, 24, .., 360
     rng = np.random.default_rng(2024 + prec)
     sample = rng.choice(s.pos.shape[0], 256, replace=False)
     _check_forces(sim, s, sample, 1e-5 if prec else 1e-11, 1e-5 if prec else 1e-10)
