@@ -2,10 +2,11 @@
 // the atomic network with its backward pass, and forces by the chain rule (eq. force).
 //
 // One wavefront per atom.  Its neighbours within r_cut are compacted into LDS; the
-// radial functions take lanes over neighbours, the angular ones lanes over the flat
-// index of the unordered pairs j < k (the summand is symmetric in j and k, so each
-// unordered pair stands for both ordered ones).  The G4 set is a grid of distinct
-// eta values (index u) and distinct (zeta, lambda) pairs (index v): per pair the
+// radial functions take lanes over neighbours, the angular ones lanes over the unordered
+// pairs j < k with R_jk < r_cut, compacted a wavefront at a time (the summand is
+// symmetric in j and k, so each unordered pair stands for both ordered ones).  The G4
+// set is a grid of distinct eta values (index u) and distinct (zeta, lambda) pairs
+// (index v): per pair the
 // lane evaluates exp(-eta_u s2) and (1 + lambda_v cos)^zeta_v once each and
 // accumulates their products on the grid, so the cost per pair does not grow with
 // the number of G4 functions that share them.
@@ -41,6 +42,7 @@ struct Nb {
   double h1[MD_BPNN_MAX_HIDDEN], h2[MD_BPNN_MAX_HIDDEN], d1[MD_BPNN_MAX_HIDDEN],
       d2[MD_BPNN_MAX_HIDDEN];
   double C[NE * NZ];
+  unsigned short pq[2 * MD_WAVE];  // queued neighbour pairs j | k << 8 (for_pairs_in_cutoff)
   int nc;
 };
 
@@ -150,6 +152,47 @@ __device__ __forceinline__ void pair_of(int t, int nc, int& j, int& k) {
   k = t - r * (2 * nc - r - 1) / 2 + r + 1;
 }
 
+// The centre atom's unordered neighbour pairs j < k with R_jk < r_cut, a wavefront at a
+// time.  Lanes test 64 flat pair indices per trip and append the accepted pairs to an LDS
+// queue; each full wavefront of queued pairs, and the remainder at the end, goes to
+// body(j, k, active).  A pair beyond the cutoff adds nothing to G4 or to its derivatives
+// (f_c(R_jk) = f_c'(R_jk) = 0), and about half the pairs of a neighbour sphere are such
+// pairs: compacting them away keeps the lanes on pairs that contribute.
+template <typename Body>
+__device__ __forceinline__ void for_pairs_in_cutoff(const BpnnDev& P, Nb& s, int nc, Body body) {
+  const int lane = threadIdx.x & (MD_WAVE - 1);
+  const int npairs = nc * (nc - 1) / 2;
+  int qn = 0;  // queued pairs (below 64 between trips)
+  for (int t0 = 0; t0 < npairs; t0 += MD_WAVE) {
+    const int t = t0 + lane;
+    bool ok = false;
+    int j = 0, k = 0;
+    if (t < npairs) {
+      pair_of(t, nc, j, k);
+      const double dx = s.ax[k] - s.ax[j], dy = s.ay[k] - s.ay[j], dz = s.az[k] - s.az[j];
+      ok = sqrt(dx * dx + dy * dy + dz * dz) < P.rc;  // the test cutoff() applies to R_jk
+    }
+    const unsigned long long m = __ballot(ok);
+    if (ok) s.pq[qn + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)(j | (k << 8));
+    qn += __popcll(m);
+    __builtin_amdgcn_wave_barrier();
+    if (qn >= MD_WAVE) {
+      const unsigned e = s.pq[lane];
+      const unsigned rest = lane < qn - MD_WAVE ? s.pq[MD_WAVE + lane] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (lane < qn - MD_WAVE) s.pq[lane] = (unsigned short)rest;
+      qn -= MD_WAVE;
+      __builtin_amdgcn_wave_barrier();
+      body((int)(e & 255u), (int)(e >> 8), true);
+    }
+  }
+  if (qn > 0) {
+    const unsigned e = lane < qn ? s.pq[lane] : 0u;
+    body((int)(e & 255u), (int)(e >> 8), lane < qn);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Pass 1: symmetry functions, E_i and dE_i/dG per atom.  NEU eta values are kept in the
 // per-lane accumulator grid (NEU x NZ registers): 6 for sets with at most six distinct
 // eta values (the common case, which leaves room for two wavefronts per SIMD), else NE.
@@ -178,31 +221,27 @@ __global__ __launch_bounds__(64 * WPB, 2) void k_bpnn_desc(md_batch b, BpnnDev P
       acc = md_wave_sum(acc);
       if (lane == 0) s.G[mu] = acc;
     }
-    // angular functions: lanes over the unordered pairs
+    // angular functions: lanes over the unordered pairs within the cutoff
     double g[NEU][NZ];
 #pragma unroll
     for (int u = 0; u < NEU; ++u)
 #pragma unroll
       for (int v = 0; v < NZ; ++v) g[u][v] = 0.0;
-    const int npairs = nc * (nc - 1) / 2;
-    for (int tp = lane; tp < npairs; tp += MD_WAVE) {
-      {
-        int j, k;
-        pair_of(tp, nc, j, k);
-        const Trip t = triplet(P, s, j, k);
-        if (t.f3 == 0.0) continue;
-        double X[NEU], Pw[NZ];
+    for_pairs_in_cutoff(P, s, nc, [&](int j, int k, bool active) {
+      if (!active) return;
+      const Trip t = triplet(P, s, j, k);
+      if (t.f3 == 0.0) return;
+      double X[NEU], Pw[NZ];
 #pragma unroll
-        for (int u = 0; u < NEU; ++u) X[u] = u < P.n_eta ? exp(-P.eta_u[u] * t.s2) * t.f3 : 0.0;
+      for (int u = 0; u < NEU; ++u) X[u] = u < P.n_eta ? exp(-P.eta_u[u] * t.s2) * t.f3 : 0.0;
 #pragma unroll
-        for (int v = 0; v < NZ; ++v)
-          Pw[v] = v < P.n_zl ? powi(1.0 + P.lam_v[v] * t.cos, P.izeta_v[v], P.zeta_v[v]) : 0.0;
+      for (int v = 0; v < NZ; ++v)
+        Pw[v] = v < P.n_zl ? powi(1.0 + P.lam_v[v] * t.cos, P.izeta_v[v], P.zeta_v[v]) : 0.0;
 #pragma unroll
-        for (int u = 0; u < NEU; ++u)
+      for (int u = 0; u < NEU; ++u)
 #pragma unroll
-          for (int v = 0; v < NZ; ++v) g[u][v] += X[u] * Pw[v];
-      }
-    }
+        for (int v = 0; v < NZ; ++v) g[u][v] += X[u] * Pw[v];
+    });
 #pragma unroll
     for (int u = 0; u < NEU; ++u)
 #pragma unroll
@@ -320,16 +359,13 @@ __global__ __launch_bounds__(64 * WPB, 3) void k_bpnn_force(md_batch b, BpnnDev 
       s.gz[m] += q * s.az[m];
     }
     __builtin_amdgcn_wave_barrier();
-    // angular terms: lanes over the unordered pairs j < k.  The pair (j, k) adds g_a to
-    // neighbour j and g_b to k; the reversed order adds the same vectors with the
-    // roles swapped, which the factor 2 in the grid weights C accounts for.  Lanes of
-    // one step can share a neighbour, so the LDS sums take atomic adds.
-    const int npairs = nc * (nc - 1) / 2;
-    for (int tp = lane; tp < npairs; tp += MD_WAVE) {
-      int j, k;
-      pair_of(tp, nc, j, k);
+    // angular terms: lanes over the unordered pairs j < k within the cutoff.  The pair
+    // (j, k) adds g_a to neighbour j and g_b to k; the reversed order adds the same
+    // vectors with the roles swapped, which the factor 2 in the grid weights C accounts
+    // for.  Lanes of one step can share a neighbour, so the LDS sums take atomic adds.
+    for_pairs_in_cutoff(P, s, nc, [&](int j, int k, bool active) {
+      if (!active) return;
       const Trip t = triplet(P, s, j, k);
-      if (t.fC == 0.0 && t.dfC == 0.0) continue;  // R_jk >= r_cut: no term, no derivative
       double X[NE], Pw[NZ], Pw1[NZ];
 #pragma unroll
       for (int u = 0; u < NE; ++u) X[u] = u < P.n_eta ? exp(-P.eta_u[u] * t.s2) : 0.0;
@@ -372,7 +408,7 @@ __global__ __launch_bounds__(64 * WPB, 3) void k_bpnn_force(md_batch b, BpnnDev 
       atomicAdd(&s.gx[k], gb[0]);
       atomicAdd(&s.gy[k], gb[1]);
       atomicAdd(&s.gz[k], gb[2]);
-    }
+    });
     __builtin_amdgcn_wave_barrier();
     // scatter: F_j -= g, F_i += sum g, W -= a (x) g
     double fi[3] = {0, 0, 0}, wv[6] = {0, 0, 0, 0, 0, 0};
