@@ -35,7 +35,7 @@ struct BpnnDev {
 // Neighbours of one atom within r_cut, compacted in LDS.
 struct Nb {
   double ax[MD_BPNN_MAX_NB], ay[MD_BPNN_MAX_NB], az[MD_BPNN_MAX_NB];
-  double R[MD_BPNN_MAX_NB], fc[MD_BPNN_MAX_NB], dfc[MD_BPNN_MAX_NB];
+  double R[MD_BPNN_MAX_NB], iR[MD_BPNN_MAX_NB], fc[MD_BPNN_MAX_NB], dfc[MD_BPNN_MAX_NB];
   double gx[MD_BPNN_MAX_NB], gy[MD_BPNN_MAX_NB], gz[MD_BPNN_MAX_NB];
   int j[MD_BPNN_MAX_NB];
   double G[MD_BPNN_MAX_G];
@@ -49,7 +49,7 @@ struct Nb {
 __device__ __forceinline__ void cutoff(double R, double rc, double& fc, double& dfc) {
   if (R < rc) {
     double s, c;
-    sincos(PI * R / rc, &s, &c);
+    sincospi(R / rc, &s, &c);  // sin and cos of pi R / r_c (argument reduction is exact)
     fc = 0.5 * (c + 1.0);
     dfc = -0.5 * PI / rc * s;
   } else {
@@ -105,6 +105,7 @@ __device__ void gather_neighbours(const BpnnDev& P, const md_domain& D, const do
       s.ay[slot] = a[1];
       s.az[slot] = a[2];
       s.R[slot] = R;
+      s.iR[slot] = 1.0 / R;  // divisions per pair become products
       s.fc[slot] = fc;
       s.dfc[slot] = dfc;
       s.gx[slot] = 0.0;
@@ -132,8 +133,8 @@ __device__ __forceinline__ Trip triplet(const BpnnDev& P, const Nb& s, int j, in
   cutoff(t.C, P.rc, t.fC, t.dfC);
   // |cos| <= 1 up to rounding; clamped so that a non-integral zeta never meets a
   // negative base
-  t.cos = fmin(1.0, fmax(-1.0, (s.ax[j] * s.ax[k] + s.ay[j] * s.ay[k] + s.az[j] * s.az[k]) /
-                                   (A * B)));
+  t.cos = fmin(1.0, fmax(-1.0, (s.ax[j] * s.ax[k] + s.ay[j] * s.ay[k] + s.az[j] * s.az[k]) *
+                                   (s.iR[j] * s.iR[k])));
   t.s2 = A * A + B * B + t.C * t.C;
   t.f3 = s.fc[j] * s.fc[k] * t.fC;
   return t;
@@ -394,13 +395,15 @@ __global__ __launch_bounds__(64 * WPB, 3) void k_bpnn_force(md_batch b, BpnnDev 
       const double sB = q1 * fA * dfB * t.fC - 2.0 * B * qe * t.f3;
       const double sC = q1 * fA * fB * t.dfC - 2.0 * Cd * qe * t.f3;
       const double aj[3] = {s.ax[j], s.ay[j], s.az[j]}, ak[3] = {s.ax[k], s.ay[k], s.az[k]};
-      const double iAB = 1.0 / (A * B), cA = t.cos / (A * A), cB = t.cos / (B * B);
+      const double iA = s.iR[j], iB = s.iR[k], iC = 1.0 / Cd;
+      const double iAB = iA * iB, cA = t.cos * (iA * iA), cB = t.cos * (iB * iB);
+      const double rA = sA * iA, rB = sB * iB, rC = sC * iC;
       double ga[3], gb[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         const double d = ak[q] - aj[q];
-        ga[q] = s_cos * (ak[q] * iAB - cA * aj[q]) + sA / A * aj[q] - sC / Cd * d;
-        gb[q] = s_cos * (aj[q] * iAB - cB * ak[q]) + sB / B * ak[q] + sC / Cd * d;
+        ga[q] = s_cos * (ak[q] * iAB - cA * aj[q]) + rA * aj[q] - rC * d;
+        gb[q] = s_cos * (aj[q] * iAB - cB * ak[q]) + rB * ak[q] + rC * d;
       }
       atomicAdd(&s.gx[j], ga[0]);
       atomicAdd(&s.gy[j], ga[1]);
