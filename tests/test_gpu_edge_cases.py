@@ -10,7 +10,9 @@
                            lies below the embedding table, so MD_ERR_TABLE_RANGE is reported
                            (the oracle flags the same atom)
   dimer                    LJ force and energy equal the closed form of eq. 1.6 (FP64 to
-                           1e-14, FP32 to 1e-6); virial equal to the oracle's
+                           1e-14, FP32 to 1e-6); virial equal to the oracle's.  EAM: energy
+                           2 F(rho(r)) + phi(r) and the pair force with both atoms' F' from the
+                           analytic forms, within the tables' interpolation error
 """
 import ctypes as C
 
@@ -181,3 +183,27 @@ def test_lj_dimer_closed_form(prec, tol):
     assert abs(rec[0] - u) <= tol * abs(u) + 2e-11
     o = core.lj(x, box, p.eps, p.sigma, p.r_cut)
     assert np.max(np.abs(rec[1:7] - o.virial)) <= tol * np.max(np.abs(o.virial)) + 2e-11
+
+
+@pytest.mark.parametrize("prec,tol_e", [(0, 1e-8), (1, 1e-6)])
+def test_eam_dimer_closed_form(prec, tol_e):
+    """Two Cu atoms 2.5 A apart: E = 2 F(rho(r)) + phi(r), and the force on each is
+    [phi'(r) + 2 F'(rho(r)) rho'(r)] along the pair (both atoms' F' enter the pair term),
+    from the analytic forms the tables sample.  Tolerances: the 2000-point splines'
+    interpolation error (about 1e-9 on E, a few 1e-7 on F' near rho = 1)."""
+    from paper_2511_22951_amd import md
+    p = mi.EAM_CU
+    box = mi.Box((0.0, 0.0, 0.0), (30.0, 30.0, 30.0), (1, 1, 1))
+    r = 2.5
+    unit = np.array([0.48, 0.6, -0.64])
+    x = np.array([[10.0, 11.0, 12.0], [10.0, 11.0, 12.0] + r * unit])
+    st, nl, rec = _run(md, [(x, box)], "eam", prec)
+    phi = p.A * np.exp(-p.alpha * (r / p.r0 - 1.0))
+    rho = np.exp(-p.beta * (r / p.r0 - 1.0))
+    dphi, drho = -p.alpha / p.r0 * phi, -p.beta / p.r0 * rho
+    e = 2.0 * -np.sqrt(rho) + phi
+    dedr = dphi + 2.0 * (-0.5 / np.sqrt(rho)) * drho
+    f = st.forces()
+    assert abs(rec[0, 0] - e) <= tol_e * abs(e)
+    assert np.max(np.abs(f[1] + dedr * unit)) <= 5e-6 * abs(dedr)
+    assert np.max(np.abs(f[0] - dedr * unit)) <= 5e-6 * abs(dedr)
