@@ -308,7 +308,8 @@ typedef struct md_drift {
  * and the kinetic energy is reduced.  If ev is not NULL the per-box record
  * {E, W[6], K} is written to ev[(step % ev_cap) * n_rep + rep] (step = the
  * control block's step counter).  drift: NULL, or the next step's kick-drift to
- * fuse (md_drift, as for md_eam_forces). */
+ * fuse (md_drift, as for md_eam_forces).  MD_FP32 takes lists with 1, 2, 4 or 8
+ * lanes per atom (16: MD_ERR_ARG); MD_FP64 all five. */
 int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec, const double* pos,
                  const md_nlist* nl, void* force, double* vel, double inv_mass, double half_dt,
                  const md_drift* drift, long long* ev, int ev_cap, void* ws, void* ctl,

@@ -917,6 +917,8 @@ extern "C" int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec
   if (!md_batch_ok(b) || !p || !pos || !nlist_ok(nl) || !force || !ws || !ctl) return MD_ERR_ARG;
   if (!(p->sigma > 0.0) || !(p->r_cut > 0.0)) return MD_ERR_ARG;
   if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
+  // FP32 takes 1-8 lanes per atom, as in md_eam_forces
+  if (prec == MD_FP32 && nl->lanes > 8) return MD_ERR_ARG;
   if (ev && ev_cap < 1) return MD_ERR_ARG;
   if (vel && !(inv_mass > 0.0)) return MD_ERR_ARG;
   DriftArgs dr;

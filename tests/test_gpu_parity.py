@@ -103,7 +103,7 @@ def test_neighbor_overflow_is_reported(mdmod):
 # ----------------------------------------------------------------------------
 # forces
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("cells,lanes", [(4, 4), (5, 1), (5, 8)])
+@pytest.mark.parametrize("cells,lanes", [(4, 4), (5, 1), (5, 8), (5, 16)])
 def test_lj_fp64_matches_oracle(mdmod, cells, lanes):
     p = mi.LJ_AR
     pos, box = displaced(cells, 5.26, 0.15, seed=11)
@@ -115,6 +115,17 @@ def test_lj_fp64_matches_oracle(mdmod, cells, lanes):
     e = evv(ev)[0, 0]
     assert abs(e[0] - r.energy) < 1e-12 * abs(r.energy)
     assert np.max(np.abs(e[1:7] - r.virial)) < 1e-11 * np.max(np.abs(r.virial))
+
+
+def test_lj_fp32_rejects_16_lanes(mdmod):
+    """FP32 takes 1-8 lanes per atom (as the EAM passes): 16 is an argument error."""
+    p = mi.LJ_AR
+    pos, box = displaced(4, 5.26, 0.15, seed=14)
+    plan, st, nl = _setup(mdmod, pos, box, p.r_cut + 0.3, lanes=16, prec=1)
+    with pytest.raises(mdmod.MDError) as e:
+        mdmod.md_lj_forces(st, mdmod.lj_params(p.eps, p.sigma, p.r_cut), nl)
+    assert e.value.status == -1
+    st.check_flags()
 
 
 def test_lj_fp32_within_tolerance(mdmod):
