@@ -177,16 +177,23 @@ def run_path(system, prec, lanes, args, k_cap=None):
     else:
         sim.run(args.warmup, graph_steps=args.graph_steps)
     sim.set_rebuild_every(k)
+    # capture the step graph for this period before the timed run (capture is set-up: the
+    # host records the launches while the GPU waits), and replay it once
+    sim.run(args.graph_steps + k, graph_steps=args.graph_steps)
     torch.cuda.synchronize()
     st0 = sim.state.read_flags()[1]
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # the timed run in five back-to-back segments (events between them, no synchronisation):
+    # the total gives `value`, the segments a median per-step time
+    seg = [args.steps // 5 + (1 if q < args.steps % 5 else 0) for q in range(5)]
+    ev_t = [torch.cuda.Event(enable_timing=True) for _ in range(len(seg) + 1)]
     torch.cuda.synchronize()
-    e0.record()
-    sim.run(args.steps, graph_steps=args.graph_steps)
-    e1.record()
+    ev_t[0].record()
+    for q, n_q in enumerate(seg):
+        sim.run(n_q, graph_steps=args.graph_steps)
+        ev_t[q + 1].record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    ms = ev_t[0].elapsed_time(ev_t[-1])
+    seg_ms = [ev_t[q].elapsed_time(ev_t[q + 1]) / max(1, n_q) for q, n_q in enumerate(seg)]
     status, info = sim.state.read_flags()
     if status == N.MD_ERR_STALE_LIST and args.rebuild_every < 0:
         raise StaleList(k)
@@ -214,6 +221,7 @@ def run_path(system, prec, lanes, args, k_cap=None):
         "energy_span_per_atom": float(np.max(etot) - np.min(etot)),
         "kernels_ms": kt, "mean_neigh": nneigh, "max_nneigh": info["max_nneigh"], "f0": f0,
         "lanes": lanes, "rebuild_every": k, "rebuild_ms": rebuild_ms,
+        "segment_ms_per_step": seg_ms,
     }
 
 
@@ -368,6 +376,8 @@ def main():
                     "energy_span_eV_per_atom": r["energy_span_per_atom"],
                     "kernel_us": {kk: 1e3 * v[0] for kk, v in r["kernels_ms"].items()},
                     "rebuild_us": 1e3 * r["rebuild_ms"],
+                    "ms_per_step_segments": r["segment_ms_per_step"],
+                    "ms_per_step_median_of_5": float(np.median(r["segment_ms_per_step"])),
                     "force_rel_err_vs_oracle": ferr.get(k)}
     if "fp32" in results and "fp64" in results:
         paths["fp32"]["force_rel_err_vs_fp64_gpu"] = float(
