@@ -316,7 +316,8 @@ int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec, const dou
                  void* stream);
 
 
-/* EAM forces: a density pass (rhobar_i = sum_j rho(r_ij), F(rhobar_i),
+/* EAM forces (Sec. 1.6: the pair force of eq. 1.6 with the embedded-atom energy,
+ * Sec. 3.3: the potential given as tables): a density pass (rhobar_i = sum_j rho(r_ij), F(rhobar_i),
  * F'(rhobar_i), the energy) then a force pass
  *   f_i = -sum_j [phi'(r) + (F'(rhobar_i) + F'(rhobar_j)) rho'(r)] r_ij / r,
  * with the virial and an optional trailing half kick as in md_lj_forces.
@@ -343,7 +344,10 @@ int md_verlet_step(const md_batch* b, md_verlet_phase phase, double dt, double* 
                    const md_walls* walls, const md_langevin* lang, const double* pos_ref,
                    double half_skin, void* ctl, void* stream);
 
-/* Vector-Jacobian product of the EAM forces with respect to the three spline
+/* Derivative of a loss of the EAM forces of md_eam_forces (Sec. 1.6, eq. 1.6) with
+ * respect to the potential's tables -- the hand-written counterpart of the automatic
+ * differentiation that gives forces from the network energy in Sec. 2.1 (eq. force).
+ * Vector-Jacobian product of the EAM forces with respect to the three spline
  * coefficient vectors: grad_coef[phi | rho | F] += sum_i G_i . dF_i/dc for a
  * cotangent G = dL/dF ([3][n] FP64).  Needs `saved` from md_eam_forces on the
  * same positions and coefficients.  Accumulation is in FP64 and deterministic.

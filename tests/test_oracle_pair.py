@@ -89,6 +89,65 @@ def test_neighbor_set_matches_dense_distance_matrix():
         assert np.array_equal(lst[i], np.nonzero(r2[i] < 7.5 ** 2)[0])
 
 
+def _dense_r2(x, box):
+    """All squared minimum-image distances by numpy broadcasting (periodic axes only get the
+    image shift), in the same operation order as the definition: (dx dx + dy dy) + dz dz."""
+    L = np.array(box.len, np.float64)
+    per = np.array(box.periodic, bool)
+    d = x[None, :, :] - x[:, None, :]
+    d = np.where(per, d - L * np.rint(d / np.where(per, L, 1.0)), d)
+    return (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+
+
+@pytest.mark.parametrize("cells,a,rns,periodic", [(3, 5.26, 7.5, (1, 1, 1)),
+                                                   (4, 3.615, 5.8, (1, 1, 1)),
+                                                   (5, 3.30, 5.8, (1, 1, 0)),
+                                                   (3, 4.05, 6.0, (0, 1, 1))])
+def test_sampled_neighbor_sets_match_brute_force(cells, a, rns, periodic):
+    """The sampled neighbour sets (used to check large systems) against a numpy distance
+    matrix and against the full oracle, for an unsorted sample with repeats that includes
+    atoms next to every face of the box (eq. 1.2)."""
+    pos, _ = mi.fcc_lattice(cells, cells, cells, a)
+    box = mi.Box((0.0, 0.0, 0.0), (cells * a,) * 3, periodic)
+    x = _disp(pos, box, 0.15, 11)
+    n = len(x)
+    r2 = _dense_r2(x, box)
+    np.fill_diagonal(r2, np.inf)
+    L = np.array(box.len)
+    near_face = np.nonzero(np.any((x < 0.6) | (x > L - 0.6), axis=1))[0]
+    rng = np.random.default_rng(cells)
+    idx = np.concatenate([rng.permutation(near_face)[:12], rng.integers(0, n, 20),
+                          [n - 1, 0, 0]]).astype(np.int32)
+    cnt, lst = core.neighbor_sets_sampled(x, box, rns, idx)
+    cnt_all, lst_all = core.neighbor_sets(x, box, rns)
+    assert len(lst) == len(idx)
+    for s, i in enumerate(idx):
+        want = np.nonzero(r2[i] < rns * rns)[0]
+        assert cnt[s] == len(want)
+        assert np.array_equal(lst[s], want)
+        assert np.array_equal(lst[s], lst_all[i])
+
+
+def test_min_gap_matches_brute_force():
+    """min over pairs of |r_ij - r_probe| against numpy's all-pairs distances, for probes
+    between, near and on shell radii, periodic and walled boxes."""
+    pos, _ = mi.fcc_lattice(3, 3, 3, 3.615)
+    for periodic in ((1, 1, 1), (1, 0, 1)):
+        box = mi.Box((0.0, 0.0, 0.0), (3 * 3.615,) * 3, periodic)
+        x = _disp(pos, box, 0.08, 21)
+        r = np.sqrt(_dense_r2(x, box))
+        iu = np.triu_indices(len(x), 1)
+        n = len(x)
+        # probes on the exact distance of chosen pairs (first, adjacent, last atoms) give a
+        # gap of zero only if that pair is visited
+        exact = [float(r[0, 1]), float(r[7, 8]), float(r[3, n - 1]), float(r[n - 2, n - 1])]
+        for probe in [2.556, 3.615 / np.sqrt(2), 4.4, 5.5] + exact:
+            want = np.min(np.abs(r[iu] - probe))
+            assert core.min_gap(x, box, probe) == pytest.approx(want, rel=0, abs=1e-12)
+        for probe in exact:
+            assert core.min_gap(x, box, probe) < 1e-12
+
+
 # ----------------------------------------------------------------------------
 # Lennard-Jones
 # ----------------------------------------------------------------------------
