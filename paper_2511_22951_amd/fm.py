@@ -48,31 +48,58 @@ class SnapshotBatch:
         md.md_eam_forces(self.state, pot, self.nl, saved=self.saved if saved else None)
         return self.state.force.double()
 
-    def backward(self, pot: md.EAMPotential, grad_force):
+    def backward(self, pot: md.EAMPotential, grad_force, saved=None):
+        """Gradient with respect to pot's current coefficients; `saved` ({rhobar, F', F''} of
+        the forward pass at those coefficients) defaults to the last forces(saved=True)."""
         g = grad_force.to(torch.float64).contiguous()
         nb = int(N.lib().md_backward_workspace_bytes(C.byref(self.plan.c), C.byref(pot.c)))
         if self.bws is None or self.bws.numel() < nb:
             self.bws = torch.zeros(max(nb, 1), dtype=torch.uint8, device=self.state.pos.device)
-        return md.md_eam_backward(self.state, pot, self.nl, self.saved, g, ws=self.bws)
+        return md.md_eam_backward(self.state, pot, self.nl, self.saved if saved is None else saved,
+                                  g, ws=self.bws)
+
+
+def _split(pot, c):
+    n0, n1 = pot.coef[0].shape[0], pot.coef[1].shape[0]
+    return c[:n0], c[n0:n0 + n1], c[n0 + n1:]
 
 
 class EAMForces(torch.autograd.Function):
     """forces = EAMForces.apply(coef, batch, potential): coef is the concatenated
-    (phi | rho | F) coefficient vector; the result is [3, n] in the batch's current order."""
+    (phi | rho | F) coefficient vector; the result is [3, n] in the batch's current order.
+
+    The state the gradient needs -- the coefficients and the forward pass's {rhobar, F',
+    F''} -- is kept per call in ctx, so forward passes at other coefficients between this
+    call and its backward (a second loss, a closure, numerical gradient checks) do not
+    change its gradient."""
 
     @staticmethod
     def forward(ctx, coef, batch: SnapshotBatch, pot: md.EAMPotential):
-        n0, n1 = pot.coef[0].shape[0], pot.coef[1].shape[0]
-        c = coef.detach().to(torch.float64)
-        pot.set_coefficients(c[:n0], c[n0:n0 + n1], c[n0 + n1:])
+        c = coef.detach().to(torch.float64).contiguous()
+        pot.set_coefficients(*_split(pot, c))
         f = batch.forces(pot, saved=True).clone()
         ctx.batch, ctx.pot = batch, pot
+        ctx.coef = c.clone()
+        ctx.saved = batch.saved.clone()
+        ctx.version = pot.version
         ctx.coef_dtype = coef.dtype
         return f
 
     @staticmethod
     def backward(ctx, grad_f):
-        g = ctx.batch.backward(ctx.pot, grad_f)
+        pot = ctx.pot
+        if pot.version == ctx.version:
+            g = ctx.batch.backward(pot, grad_f, saved=ctx.saved)
+        else:
+            # a later forward changed the coefficients: differentiate at this call's, then
+            # put the later ones back (with their version, so their own backward stays direct)
+            later, later_version = torch.cat([c.clone() for c in pot.coef]), pot.version
+            pot.set_coefficients(*_split(pot, ctx.coef))
+            try:
+                g = ctx.batch.backward(pot, grad_f, saved=ctx.saved)
+            finally:
+                pot.set_coefficients(*_split(pot, later))
+                pot.version = later_version
         return g.to(ctx.coef_dtype), None, None
 
 

@@ -203,6 +203,7 @@ class EAMPotential:
         self.r_cut = float(r_cut)
         self.device = dev
         self._tables = {}
+        self.version = 0  # advanced by every coefficient change
         self._build_struct()
 
     def _build_struct(self):
@@ -226,6 +227,7 @@ class EAMPotential:
             if c is not None:
                 self.coef[k].copy_(torch.as_tensor(c, dtype=torch.float64))
         self._tables = {}
+        self.version += 1
         self._build_struct()
 
     def table(self, precision):

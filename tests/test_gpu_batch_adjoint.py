@@ -179,3 +179,28 @@ def test_force_matching_gradient_matches_oracle_and_fd(md):
         lm = fm.force_matching_loss(cm, batch, pot, f_ref).item()
         fd = (lp - lm) / (2 * h)
         assert abs(fd - got[k]) < 1e-5 * np.max(np.abs(got)), (k, fd, got[k])
+
+
+def test_force_matching_backward_after_another_forward(md):
+    """Two losses at different coefficients, then backward of the first: its gradient equals
+    that of a forward-backward at the first coefficients alone, bit for bit."""
+    from paper_2511_22951_amd import fm
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, n_snap=2)
+    ref_pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
+    f_ref = batch.forces(ref_pot, saved=False).clone()
+    c1 = torch.cat([c.clone() for c in pot.coef])
+    c2 = c1 * 1.01
+    a = c1.clone().requires_grad_(True)
+    fm.force_matching_loss(a, batch, pot, f_ref).backward()
+    want = a.grad.clone()
+    b1 = c1.clone().requires_grad_(True)
+    b2 = c2.clone().requires_grad_(True)
+    l1 = fm.force_matching_loss(b1, batch, pot, f_ref)
+    l2 = fm.force_matching_loss(b2, batch, pot, f_ref)
+    l1.backward()
+    assert torch.equal(b1.grad, want)
+    assert torch.equal(torch.cat(pot.coef), c2)  # the later coefficients are back in place
+    l2.backward()
+    b2_alone = c2.clone().requires_grad_(True)
+    fm.force_matching_loss(b2_alone, batch, pot, f_ref).backward()
+    assert torch.equal(b2.grad, b2_alone.grad)
