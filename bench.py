@@ -3,17 +3,20 @@
 Workload: EAM Cu, fcc 32^3 cells = 131,072 atoms, a = 3.615 A, N(0, 0.05^2) A
 displacements, 300 K velocities, dt = 1 fs, skin 0.3 A (r_ns = 5.8 A), 2000-point
 spline tables; velocity Verlet with neighbour lists rebuilt every k steps, k taken from a
-warm-up on the half-skin threshold and the criterion verified on every step (a run whose
-list went stale is void and repeated with a shorter k); energies and virial reduced every
-step.  A step is the whole hot path: kick-drift + displacement check, binning and list
-build when due, EAM density pass, EAM force pass with the trailing kick and reductions
-(the next kick-drift fused into it).
+120-step warm-up on the half-skin threshold (independent of --warmup) and the criterion
+verified on every step (a run whose list went stale is void and repeated with a shorter
+k); energies and virial reduced every step.  A step is the whole hot path: kick-drift +
+displacement check, binning and list build when due, EAM density pass, EAM force pass
+with the trailing kick and reductions (the next kick-drift fused into it).
 
 Two GPU paths are timed: FP32-mixed (FP32 pair arithmetic and force sums, FP64
 positions/integration/reductions) -- the headline `value` -- and plain FP64.
-The timed region replays HIP graphs of `--graph-steps` steps; inputs are resident
-in HBM.  Kernel durations for the roofline are taken live with HIP events placed
-by the library around single launches (hipExtLaunchKernelGGL).
+The timed region is exactly --steps steps, all of them HIP-graph replays: a graph of
+whole rebuild periods (about --graph-steps steps) replayed as often as it fits and one
+tail graph for the remainder, both captured before the timed region; inputs are resident
+in HBM.  Kernel durations for the roofline are taken live with HIP events placed by the
+library around single launches (hipExtLaunchKernelGGL).  The NVE drift comes from an
+untimed run of --drift-steps steps after the timed one.
 
 `cpu_baseline` times the FP64 O(N^2) oracle (one full step of the same state) on
 the host cores; it is the only part of this script that touches the oracle.
@@ -42,6 +45,8 @@ def parse():
                     help="timed steps (default: 1000; 5000 for al_shock)")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--graph-steps", type=int, default=50)
+    ap.add_argument("--drift-steps", type=int, default=1000,
+                    help="NVE steps of the untimed run whose total energy gives the drift")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: autotune)")
     ap.add_argument("--kernel-samples", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -80,11 +85,34 @@ FORCE_SOURCES = ("paper_2511_22951_amd/csrc/md_force.hip", "paper_2511_22951_amd
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eam_cu131k_hbm_traffic.txt")
 
 
+def strip_c_comments(text):
+    """C/C++ source without its comments and blank lines (string literals in these sources
+    hold no comment markers)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+
+
+def force_source_digest(read=None):
+    """SHA-256 of the force-pass sources with comments removed: a counter summary stays
+    current while only comments change.  read(name) -> text (default: the working tree)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in FORCE_SOURCES:
+        if read is None:
+            with open(os.path.join(ROOT, name)) as f:
+                text = f.read()
+        else:
+            text = read(name)
+        h.update(strip_c_comments(text).encode())
+    return h.hexdigest()
+
+
 def measured_traffic(prec_name, lanes):
     """HBM bytes per force-pass launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE scaled by a copy calibration), or None when the summary was taken for
     another configuration or the force-pass sources have changed since."""
-    import hashlib
     try:
         kv = {}
         with open(TRAFFIC_FILE) as f:
@@ -93,13 +121,10 @@ def measured_traffic(prec_name, lanes):
             if " = " in line:
                 k, v = line.split(" = ", 1)
                 kv[k.strip()] = v.strip()
-        h = hashlib.sha256()
-        for name in FORCE_SOURCES:
-            with open(os.path.join(ROOT, name), "rb") as f:
-                h.update(f.read())
+        digest = force_source_digest()
     except OSError:
         return None
-    if kv.get("source_sha256") != h.hexdigest():
+    if kv.get("source_sha256") != digest:
         return None
     if (kv.get("precision") != prec_name or kv.get("lanes") != str(lanes)
             or "k_eam_force_traffic_bytes" not in kv):
@@ -147,63 +172,100 @@ def with_valid_period(run, name=""):
     return result
 
 
+PERIOD_WARMUP_STEPS = 120  # threshold-policy steps that choose the rebuild period (untimed)
+
+
+def rebuild_period(marks, base, k_cap=None):
+    """The fixed rebuild period k from a threshold-policy warm-up: marks[s] is the rebuild
+    count after warm-up step s + 1, base the count before it (the lists were built just
+    before step 1).  k = 4/5 of the shortest interval between builds, at most 20; with no
+    threshold rebuild in the warm-up, 4/5 of its length (the lists stayed valid that long).
+    k_cap bounds k (void runs).  Returns (k, warm-up steps that rebuilt)."""
+    prev = [base] + list(marks[:-1])
+    at = [0] + [s + 1 for s in range(len(marks)) if marks[s] > prev[s]]
+    gaps = np.diff(at) if len(at) > 1 else np.array([len(marks)])
+    k = int(max(1, min(20, np.floor(0.8 * gaps.min()))))
+    if k_cap is not None:
+        k = max(1, min(k, k_cap))
+    return k, at[1:]
+
+
+def timed_graph_run(sim, steps, graph_steps):
+    """Exactly `steps` steps as graph replays only (Simulation.prepare_timed): a main graph
+    of whole rebuild periods replayed q times and one tail graph for the remainder.  The
+    graphs are captured (and the main one replayed once) before the timed region; events
+    bracket every replay on the current stream.  Returns (ms, per-step ms of each replay,
+    description); raises if a step ran eagerly inside the timed region."""
+    import torch
+    from paper_2511_22951_amd.sim import timed_graph_plan
+    sim.align()
+    G, q, r = timed_graph_plan(steps, sim.rebuild_every, sim.fused, graph_steps)
+    plan = sim.prepare_timed(steps, graph_steps)
+    if q:  # upload and warm the main graph (keeps the phase and the buffer arrangement)
+        plan[0][0].replay()
+        sim.n_steps += plan[0][1]
+    ev_t = [torch.cuda.Event(enable_timing=True) for _ in range(len(plan) + 1)]
+    torch.cuda.synchronize()
+    eager0 = sim.eager_steps
+    sim.replay_timed(plan, ev_t)
+    torch.cuda.synchronize()
+    if sim.eager_steps != eager0:
+        raise RuntimeError("a step ran outside the graphs in the timed region")
+    ms = ev_t[0].elapsed_time(ev_t[-1]) if plan else 0.0
+    per = [ev_t[j].elapsed_time(ev_t[j + 1]) / n for j, (_, n) in enumerate(plan)]
+    desc = {"graph_steps": G if q else 0, "main_replays": q, "tail_graph_steps": r,
+            "eager_steps_timed": 0}
+    return ms, per, desc
+
+
 def run_path(system, prec, lanes, args, k_cap=None):
     import torch
     from paper_2511_22951_amd import _native as N
     from paper_2511_22951_amd.sim import Simulation
 
-    cap = args.warmup + args.steps + args.kernel_samples + 8
+    n = system.pos.shape[0]
+    cap = (PERIOD_WARMUP_STEPS + args.warmup + args.steps + args.drift_steps
+           + args.kernel_samples + 2 * args.graph_steps + 64)
     sim = Simulation(system, precision=prec, lanes=lanes, ev_cap=cap,
                      fused=not args.unfused).setup()
     torch.cuda.synchronize()
     f0 = sim.state.forces()
-    # Warm-up on the threshold policy, recording when rebuilds happen; then rebuild every
-    # k steps with k = 4/5 of the shortest interval seen.  The half-skin criterion stays
-    # verified on every step: a timed run that used a stale list raises MD_ERR_STALE_LIST,
-    # and the caller then repeats the path with a shorter period (k_cap).
+    epot0 = float(sim.energies([0])[0][0]) / n  # step 0: the initial state
+    # A threshold-policy warm-up of fixed length records when rebuilds happen; then lists
+    # are rebuilt every k steps.  The half-skin criterion stays verified on every step: a
+    # timed run that used a stale list raises MD_ERR_STALE_LIST, and the caller repeats the
+    # path with a shorter period (k_cap).
     k = args.rebuild_every
     if k < 0:
-        marks = []
-        for _ in range(args.warmup):
+        base, marks = sim.state.read_flags()[1]["n_rebuilds"], []
+        for _ in range(PERIOD_WARMUP_STEPS):
             sim.step()
             marks.append(sim.state.read_flags()[1]["n_rebuilds"])
-        at = [s for s in range(1, len(marks)) if marks[s] > marks[s - 1]]
-        gaps = np.diff(at) if len(at) > 1 else np.array([10])
-        k = int(max(1, min(20, np.floor(0.8 * gaps.min()))))
-        if k_cap is not None:
-            k = max(1, min(k, k_cap))
-        print("[bench] warm-up rebuilds at steps %s -> rebuild every %d steps" % (at, k),
-              file=sys.stderr, flush=True)
-    else:
-        sim.run(args.warmup, graph_steps=args.graph_steps)
+        k, at = rebuild_period(marks, base, k_cap)
+        print("[bench] %d-step threshold warm-up: rebuilds at steps %s -> rebuild every %d steps"
+              % (PERIOD_WARMUP_STEPS, at, k), file=sys.stderr, flush=True)
     sim.set_rebuild_every(k)
-    # capture the step graph for this period before the timed run (capture is set-up: the
-    # host records the launches while the GPU waits), and replay it once
-    sim.run(args.graph_steps + k, graph_steps=args.graph_steps)
+    sim.run(args.warmup, graph_steps=args.graph_steps)  # the --warmup steps, at period k
     torch.cuda.synchronize()
     st0 = sim.state.read_flags()[1]
-    # the timed run in five back-to-back segments (events between them, no synchronisation):
-    # the total gives `value`, the segments a median per-step time
-    seg = [args.steps // 5 + (1 if q < args.steps % 5 else 0) for q in range(5)]
-    ev_t = [torch.cuda.Event(enable_timing=True) for _ in range(len(seg) + 1)]
-    torch.cuda.synchronize()
-    ev_t[0].record()
-    for q, n_q in enumerate(seg):
-        sim.run(n_q, graph_steps=args.graph_steps)
-        ev_t[q + 1].record()
-    torch.cuda.synchronize()
-    ms = ev_t[0].elapsed_time(ev_t[-1])
-    seg_ms = [ev_t[q].elapsed_time(ev_t[q + 1]) / max(1, n_q) for q, n_q in enumerate(seg)]
+    ms, per_replay, timed_desc = timed_graph_run(sim, args.steps, args.graph_steps)
     status, info = sim.state.read_flags()
     if status == N.MD_ERR_STALE_LIST and args.rebuild_every < 0:
         raise StaleList(k)
     N.check(status, "device flags after the timed run")
-    steps = list(range(st0["step"], info["step"] + 1))
+    rebuilds = info["n_rebuilds"] - st0["n_rebuilds"]
+    # NVE drift over a run of its own (untimed, graphs): total energy per atom against time
+    s0 = info["step"]
+    sim.run(args.drift_steps, graph_steps=args.graph_steps)
+    status, info = sim.state.read_flags()
+    if status == N.MD_ERR_STALE_LIST and args.rebuild_every < 0:
+        raise StaleList(k)
+    N.check(status, "device flags after the drift run")
+    steps = list(range(s0, info["step"] + 1))
     ev = sim.energies(steps)
-    n = system.pos.shape[0]
     etot = (ev[:, 0] + ev[:, 7]) / n
     tps = np.array(steps) * system.dt_ps
-    slope = float(np.polyfit(tps - tps[0], etot, 1)[0])
+    slope = float(np.polyfit(tps - tps[0], etot, 1)[0]) if len(steps) > 2 else None
     # live kernel timing of the EAM passes and the kick-drift kernel
     kt = {}
     knames = ("eam_force", "eam_density", "build") + (() if sim.fused else ("kick_drift",))
@@ -216,12 +278,12 @@ def run_path(system, prec, lanes, args, k_cap=None):
     rebuild_ms = _gpu_time(lambda: sim.rebuild(), 5) / 5  # binning + list, after the run
     torch.cuda.synchronize()
     return {
-        "ms": ms, "steps": args.steps, "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"],
-        "drift_ev_per_atom_ps": slope, "e0_per_atom": float(etot[0]),
+        "ms": ms, "steps": args.steps, "rebuilds": rebuilds, "timed": timed_desc,
+        "drift_ev_per_atom_ps": slope, "drift_steps": len(steps) - 1, "epot0_per_atom": epot0,
         "energy_span_per_atom": float(np.max(etot) - np.min(etot)),
         "kernels_ms": kt, "mean_neigh": nneigh, "max_nneigh": info["max_nneigh"], "f0": f0,
         "lanes": lanes, "rebuild_every": k, "rebuild_ms": rebuild_ms,
-        "segment_ms_per_step": seg_ms,
+        "replay_ms_per_step": per_replay,
     }
 
 
@@ -325,10 +387,17 @@ def main():
     R = results[head]
     ms_step = R["ms"] / args.steps
     value = n * args.steps / (R["ms"] * 1e-3)
-    fb = 4 if head == "fp32" else 8
-    kt_force = R["kernels_ms"]["eam_force"][0] * 1e-3
-    bytes_force = algorithmic_force_bytes(n, R["mean_neigh"], fb, fused=not args.unfused)
-    achieved = bytes_force / kt_force / 1e9
+
+    def roofline(name):
+        r = results[name]
+        kt = r["kernels_ms"]["eam_force"][0] * 1e-3
+        nbytes = algorithmic_force_bytes(n, r["mean_neigh"], 4 if name == "fp32" else 8,
+                                         fused=not args.unfused)
+        a = nbytes / kt / 1e9
+        return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": a / HBM_PEAK_GBS, "traffic": measured_traffic(name, r["lanes"]),
+                "kernel": "k_eam_force_" + ("f32" if name == "fp32" else "f64"),
+                "kernel_us": kt * 1e6, "bytes_per_launch": nbytes}
 
     f_gpu = {k: r["f0"] for k, r in results.items()}
     if args.no_cpu_baseline:
@@ -352,32 +421,34 @@ def main():
         "config": {"workload": "EAM Cu fcc 32^3 = 131072 atoms, a 3.615, 300 K, dt 1 fs, "
                                "skin 0.3, 2000-point splines, NVE velocity Verlet",
                    "n_atoms": n, "precision": head, "lanes_per_atom": R["lanes"],
-                   "graph_steps": args.graph_steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(head, R["lanes"]),
-                     "kernel": "k_eam_force", "kernel_us": kt_force * 1e6,
-                     "bytes_per_launch": bytes_force,
-                     "copy_ceiling_GBs": copy_ceiling_gbs()},
+                   "timed_region": R["timed"]},
+        "roofline": dict(roofline(head), copy_ceiling_GBs=copy_ceiling_gbs()),
         "cpu_baseline": cpu,
     }
+    if head != "fp64" and "fp64" in results:
+        out["roofline_fp64"] = roofline("fp64")
     paths = {}
     for k, r in results.items():
         paths[k] = {"atom_steps_per_s": n * args.steps / (r["ms"] * 1e-3),
                     "ms_per_step": r["ms"] / args.steps, "lanes": r["lanes"],
                     "rebuilds": r["rebuilds"], "mean_neigh": r["mean_neigh"],
                     "kick_drift": "fused into the force pass" if not args.unfused else "own pass",
-                    "rebuild_policy": ("every %d steps (4/5 of the shortest warm-up interval "
-                                       "on the threshold), half-skin criterion verified every "
-                                       "step (no violation; %d void runs repeated)"
-                                       % (r["rebuild_every"], r.get("retries", 0))
+                    "rebuild_policy": ("every %d steps (4/5 of the shortest interval of a %d-step "
+                                       "warm-up on the threshold), half-skin criterion verified "
+                                       "every step (no violation; %d void runs repeated)"
+                                       % (r["rebuild_every"], PERIOD_WARMUP_STEPS,
+                                          r.get("retries", 0))
                                        if r["rebuild_every"] > 0 else "on the half-skin threshold"),
+                    "timed_region": r["timed"],
+                    "ms_per_step_of_each_replay": r["replay_ms_per_step"],
                     "nve_drift_eV_per_atom_ps": r["drift_ev_per_atom_ps"],
+                    "nve_drift_steps": r["drift_steps"],
                     "energy_span_eV_per_atom": r["energy_span_per_atom"],
                     "kernel_us": {kk: 1e3 * v[0] for kk, v in r["kernels_ms"].items()},
                     "rebuild_us": 1e3 * r["rebuild_ms"],
-                    "ms_per_step_segments": r["segment_ms_per_step"],
-                    "ms_per_step_median_of_5": float(np.median(r["segment_ms_per_step"])),
+                    "epot0_per_atom": r["epot0_per_atom"],
+                    "energy_err_per_atom_vs_oracle": (None if e_or is None
+                                                      else abs(r["epot0_per_atom"] - e_or)),
                     "force_rel_err_vs_oracle": ferr.get(k)}
     if "fp32" in results and "fp64" in results:
         paths["fp32"]["force_rel_err_vs_fp64_gpu"] = float(
@@ -385,7 +456,7 @@ def main():
             / np.linalg.norm(results["fp64"]["f0"]))
         paths["speedup_fp32_over_fp64"] = results["fp64"]["ms"] / results["fp32"]["ms"]
     if e_or is not None:
-        paths["oracle_e0_per_atom"] = e_or
+        paths["oracle_epot0_per_atom"] = e_or
     out["paths"] = paths
     print(json.dumps(out), flush=True)
 
@@ -435,13 +506,13 @@ def bench_al_shock(args):
     n = system.pos.shape[0]
     steps = args.steps or system.n_steps
     lanes = args.lanes or autotune_lanes(system, N.MD_FP32)
-    cap = args.warmup + steps + args.kernel_samples + 8
+    cap = args.warmup + steps + args.kernel_samples + 2 * args.graph_steps + 64
     sim = Simulation(system, precision=N.MD_FP32, lanes=lanes, max_neigh=160, ev_cap=cap,
                      rebuild_every=0, fused=not args.unfused).setup()
     sim.run(args.warmup, graph_steps=args.graph_steps)
     torch.cuda.synchronize()
     st0 = sim.state.read_flags()[1]
-    ms = _gpu_time(lambda: sim.run(steps, graph_steps=args.graph_steps), 1)
+    ms, _, timed_desc = timed_graph_run(sim, steps, args.graph_steps)
     status, info = sim.state.read_flags()
     N.check(status, "device flags after the timed run")
     kt = {}
@@ -534,14 +605,14 @@ def bench_lj_paper(args):
         cands = tuple(l for l in tune.CANDIDATES
                       if args.unfused or fused_grid_fits(n_tiles, l))
         lanes = args.lanes or tune.best_lanes(system, prec, candidates=cands)
-        cap = warm + steps + args.kernel_samples + 8
+        cap = warm + steps + args.kernel_samples + 2 * gs + 64
         sim = Simulation(system, precision=prec, lanes=lanes, max_neigh=112, ev_cap=cap,
                          rebuild_every=k, fused=not args.unfused).setup()
         f_gpu[name] = sim.state.forces()[sample]
         sim.run(warm, graph_steps=gs)
         torch.cuda.synchronize()
         st0 = sim.state.read_flags()[1]
-        ms = _gpu_time(lambda: sim.run(steps, graph_steps=gs), 1)
+        ms, _, timed_desc = timed_graph_run(sim, steps, gs)
         status, info = sim.state.read_flags()
         N.check(status, "device flags after the timed run")
         ev = sim.energies(range(st0["step"], info["step"] + 1))
@@ -617,13 +688,13 @@ def bench_nvt(args):
     lang = {"seed": 2511, "regions": [{"T": 300.0, "gamma": 0.5}]}
     res = {}
     for name, thermo in (("nvt", lang), ("nve", None)):
-        cap = args.warmup + steps + args.kernel_samples + 8
+        cap = args.warmup + steps + args.kernel_samples + 2 * gs + 64
         sim = Simulation(system, precision=N.MD_FP32, lanes=lanes, ev_cap=cap, rebuild_every=k,
                          thermostat=thermo).setup()
         sim.run(args.warmup, graph_steps=gs)
         torch.cuda.synchronize()
         st0 = sim.state.read_flags()[1]
-        ms = _gpu_time(lambda: sim.run(steps, graph_steps=gs), 1)
+        ms, _, timed_desc = timed_graph_run(sim, steps, gs)
         status, info = sim.state.read_flags()
         N.check(status, "device flags after the timed run")
         ev = sim.energies(range(info["step"] - steps + 1, info["step"] + 1))
@@ -692,11 +763,11 @@ def bench_bpnn(args):
     warm = min(args.warmup, 20)
     gs = min(args.graph_steps, 10)
     lanes = args.lanes or 4
-    sim = Simulation(system, precision=N.MD_FP64, lanes=lanes, ev_cap=warm + steps + 64).setup()
+    sim = Simulation(system, precision=N.MD_FP64, lanes=lanes, ev_cap=warm + steps + 2 * gs + 64).setup()
     sim.run(warm, graph_steps=gs)
     torch.cuda.synchronize()
     st0 = sim.state.read_flags()[1]
-    ms = _gpu_time(lambda: sim.run(steps, graph_steps=gs), 1)
+    ms, _, timed_desc = timed_graph_run(sim, steps, gs)
     status, info = sim.state.read_flags()
     N.check(status, "device flags after the timed run")
     ev = sim.energies(range(st0["step"] + 1, info["step"] + 1))

@@ -37,6 +37,29 @@ from . import _native as N
 from . import md
 
 
+def graph_period(rebuild_every, fused):
+    """Steps after which a captured step sequence repeats exactly: the rebuild period k
+    (rebuilds on the steps n with (n + 1) % k == 0), times 2 in fused mode when k is odd
+    (the two position buffers trade places every step)."""
+    k = max(1, int(rebuild_every))
+    return 2 * k // math.gcd(2, k) if fused else k
+
+
+def timed_graph_plan(n_steps, rebuild_every, fused, graph_steps):
+    """How a run of exactly n_steps steps, starting at a multiple of the graph period, is
+    made of graph replays only: q replays of a main graph of G steps (a multiple of the
+    period near graph_steps, at most n_steps) and, if r = n_steps - q G > 0, one replay of a
+    tail graph of r steps.  Returns (G, q, r)."""
+    n_steps = int(n_steps)
+    if n_steps < 0:
+        raise ValueError("negative step count")
+    P = graph_period(rebuild_every, fused)
+    G = P * max(1, min(int(graph_steps), n_steps) // P)
+    if G > n_steps:  # shorter than one period: the tail graph alone
+        return G, 0, n_steps
+    return G, n_steps // G, n_steps % G
+
+
 def fused_grid_fits(n_tiles, lanes):
     """Whether a force pass of `lanes` lanes per atom over n_tiles tiles (16 / lanes tiles per
     1024-thread block, the grid rounded up to a multiple of 8) fits the displacement slots
@@ -93,6 +116,8 @@ class Simulation:
             self.table = self.pot.table(precision)
         self.graph = None
         self.graph_steps = 0
+        self.eager_steps = 0  # steps launched outside graph capture (timed-region checks)
+        self._capturing = False
 
     # -- pieces ---------------------------------------------------------------
     def forces(self, kick, ev=True):
@@ -159,6 +184,8 @@ class Simulation:
         else:
             self.forces(kick=True, ev=ev)
         self.n_steps += 1
+        if not self._capturing:
+            self.eager_steps += 1
 
     def previous_positions(self):
         """Fused mode: positions at the last completed step (x(n)), by original id."""
@@ -167,28 +194,83 @@ class Simulation:
         return self.pos_alt[:, :3].cpu().numpy()[self.state._order()]
 
     # -- graphs ---------------------------------------------------------------
-    def capture(self, steps, ev=True):
+    def capture(self, steps, ev=True, tail=False):
         """Capture `steps` consecutive steps into one graph (for rebuild_every = k the graph
         must start at a multiple of k and span a multiple of k steps; in fused mode it must
         span an even number of steps, after at least one step, so that the two position
-        buffers are back in place at the end of each replay)."""
+        buffers are back in place at the end of each replay).
+
+        tail=True captures a graph that is replayed exactly once, as the last graph of a
+        timed run (see prepare_timed): it may span any number of steps from an aligned
+        start; it is returned and not kept as self.graph."""
         k = self.rebuild_every
-        if k > 0 and (steps % k or self.n_steps % k):
+        if k > 0 and ((steps % k and not tail) or self.n_steps % k):
             raise ValueError("graph of %d steps at step %d does not align with rebuilds every %d"
                              % (steps, self.n_steps, k))
-        if self.fused and (steps % 2 or not self.primed):
+        if self.fused and ((steps % 2 and not tail) or not self.primed):
             raise ValueError("fused mode: graphs span an even number of steps, after the first")
         n0 = self.n_steps
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=s):
-            for _ in range(steps):
-                self.step(ev)
+        self._capturing = True
+        try:
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(steps):
+                    self.step(ev)
+        finally:
+            self._capturing = False
         torch.cuda.current_stream().wait_stream(s)
         self.n_steps = n0  # capture recorded the steps; replays perform them
-        self.graph, self.graph_steps = g, steps
+        if not tail:
+            self.graph, self.graph_steps = g, steps
         return g
+
+    def prepare_timed(self, n_steps, graph_steps, ev=True):
+        """Graphs for a run of exactly n_steps steps made of replays only
+        (timed_graph_plan): the main graph of G steps (captured now, and kept) and, when
+        n_steps is not a multiple of G, a tail graph.  The run must start at a multiple of
+        the graph period (after the first step in fused mode).  Returns the replay list
+        [(graph, steps), ...]; run it with replay_timed() before any other step: capturing
+        a tail of an odd number of fused steps leaves the position buffers as they will be
+        after the whole run."""
+        k = max(1, self.rebuild_every)
+        if self.n_steps % k or (self.fused and not self.primed):
+            raise ValueError("a timed run starts at a multiple of the rebuild period %d" % k)
+        G, q, r = timed_graph_plan(n_steps, self.rebuild_every, self.fused, graph_steps)
+        plan = []
+        if q:
+            if self.graph is None or self.graph_steps != G:
+                self.capture(G, ev)
+            plan += [(self.graph, G)] * q
+        if r:
+            plan.append((self.capture(r, ev, tail=True), r))
+            if self.fused and r % 2:
+                # the buffers end the run swapped: the main graph (held by the plan) must not
+                # be replayed after it, so later runs capture afresh
+                self.graph, self.graph_steps = None, 0
+        return plan
+
+    def align(self, ev=True):
+        """Eager steps until the next step starts a rebuild period (and, in fused mode, the
+        first step is done); returns how many were taken."""
+        k = max(1, self.rebuild_every)
+        taken = 0
+        while (self.fused and not self.primed) or self.n_steps % k:
+            self.step(ev)
+            taken += 1
+        return taken
+
+    def replay_timed(self, plan, events=None):
+        """Replay a prepare_timed() list; events (optional, len(plan) + 1 torch events) are
+        recorded before the first and after every replay."""
+        if events is not None:
+            events[0].record()
+        for q, (g, steps) in enumerate(plan):
+            g.replay()
+            self.n_steps += steps
+            if events is not None:
+                events[q + 1].record()
 
     def run(self, n_steps, graph_steps=0, ev=True):
         k = self.rebuild_every

@@ -58,3 +58,37 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_timed_run_is_whole_graphs(fused):
+    """Every step count splits into q replays of a main graph of whole graph periods plus at
+    most one tail graph, so the timed region never steps eagerly."""
+    from paper_2511_22951_amd.sim import graph_period, timed_graph_plan
+    for k in range(0, 21):
+        P = graph_period(k, fused)
+        assert P % max(1, k) == 0 and (not fused or P % 2 == 0)
+        for steps in (0, 1, 3, 5, 20, 23, 48, 100, 1000, 1001):
+            for gs in (1, 10, 50):
+                G, q, r = timed_graph_plan(steps, k, fused, gs)
+                assert G % P == 0 and G >= P
+                assert q * G + r == steps
+                assert (q == 0 and r == steps) or 0 <= r < G
+                assert G <= max(P, steps)
+
+
+def test_rebuild_period_from_the_threshold_warm_up():
+    # builds before step 1 (count 1), then at steps 17, 35, 52: shortest interval 17 -> 13
+    marks, c = [], 1
+    for s in range(1, 121):
+        c += s in (17, 35, 52)
+        marks.append(c)
+    k, at = bench.rebuild_period(marks, base=1)
+    assert at == [17, 35, 52] and k == int(0.8 * 17)
+    # the cap of a repeated (void) run
+    assert bench.rebuild_period(marks, base=1, k_cap=9)[0] == 9
+    # no rebuild in 120 steps: the lists stayed valid throughout -> 4/5 of it, at most 20
+    assert bench.rebuild_period([1] * 120, base=1) == (20, [])
+    assert bench.rebuild_period([1] * 10, base=1) == (8, [])
+    # a rebuild on the first warm-up step counts
+    assert bench.rebuild_period([2, 2, 2, 3], base=1)[1] == [1, 4]

@@ -308,6 +308,37 @@ def test_fused_kick_drift_equals_separate(mdmod, prec, policy):
     assert np.array_equal(a.state.velocities(), b.state.velocities())
 
 
+@pytest.mark.parametrize("fused,k,steps", [(True, 5, 23), (True, 6, 20), (False, 5, 23)])
+def test_graph_only_timed_run_equals_eager(mdmod, fused, k, steps):
+    """The benchmark's timed region (Simulation.prepare_timed / replay_timed): a main graph
+    of whole graph periods replayed q times plus one tail graph -- of an odd number of steps
+    in the fused cases with k = 5 -- gives the same bits as the same steps taken eagerly, takes
+    no eager step, and leaves the state ready for further steps (EAM Cu FP32)."""
+    from paper_2511_22951_amd.sim import Simulation, timed_graph_plan
+    s = mi.eam_copper(cells=6)
+    a = Simulation(s, precision=1, lanes=2, rebuild_every=k, fused=fused).setup()
+    b = Simulation(s, precision=1, lanes=2, rebuild_every=k, fused=fused).setup()
+    for sim in (a, b):
+        sim.run(7)
+        sim.align()
+    assert a.n_steps == b.n_steps
+    G, q, r = timed_graph_plan(steps, k, fused, 10)
+    assert q >= 1 and r > 0 and (not fused or k % 2 == 0 or r % 2 == 1)
+    plan = b.prepare_timed(steps, 10)
+    e0 = b.eager_steps
+    b.replay_timed(plan)
+    assert b.eager_steps == e0 and len(plan) == q + 1
+    a.run(steps)
+    for _ in range(2):
+        ia, ib = a.state.check_flags(), b.state.check_flags()
+        assert ia["step"] == ib["step"] and ia["n_rebuilds"] == ib["n_rebuilds"] > 1
+        assert np.array_equal(a.state.positions(), b.state.positions())
+        assert np.array_equal(a.state.velocities(), b.state.velocities())
+        assert np.array_equal(a.energies(range(ia["step"] + 1)), b.energies(range(ib["step"] + 1)))
+        a.run(7)  # then further steps (graphs where whole ones fit) on both
+        b.run(7, graph_steps=10)
+
+
 @pytest.mark.parametrize("prec,policy", [(0, 0), (1, 5)])
 def test_fused_kick_drift_lj_equals_separate(mdmod, prec, policy):
     """The same for the LJ pass: argon 4^3 cells (256 atoms) at 300 K, 30 steps."""
