@@ -15,7 +15,9 @@
 // block / global reductions are FP64.
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "md_internal.h"
 #include "md_tables.h"
@@ -748,15 +750,34 @@ bool md_big_list(const md_nlist& nl, int npad) {
   return (size_t)nl.max_neigh * (size_t)npad >= ((size_t)1 << 30);
 }
 
-// FP32 tables are staged in LDS when they fit the default dynamic LDS limit
-// (2 blocks of 1024 threads per CU); FP64 tables are read through the caches.
+// Pair tables are staged in LDS when they fit beside the kernels' static LDS: the
+// FP32 rows of the r^2 grid (62.5 KB) and the FP64 rows of 2000-point splines
+// (125 KB; gfx950 has 160 KB of LDS per CU).  Read through the caches instead, the
+// FP64 rows cost four vector-memory lookups per pair, which bound the FP64 passes by
+// the L1 tag rate.
+constexpr size_t MD_LDS_TABLE_MAX = 144 * 1024;
 template <typename R>
 bool table_in_lds(int nrows, int width) {
-  return sizeof(R) == 4 && (size_t)nrows * width * sizeof(R) <= 65536;
+  return (size_t)nrows * width * sizeof(R) <= MD_LDS_TABLE_MAX;
+}
+
+// Dynamic LDS above 64 KB is allowed per kernel function, once.
+int allow_big_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return MD_OK;
+  static std::mutex mu;
+  static std::vector<const void*> done;
+  std::lock_guard<std::mutex> lock(mu);
+  for (const void* f : done)
+    if (f == fn) return MD_OK;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MD_LDS_TABLE_MAX) !=
+      hipSuccess)
+    return MD_ERR_HIP;
+  done.push_back(fn);
+  return MD_OK;
 }
 
 template <typename R, int LANES>
-void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_table_layout& TL,
+int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_table_layout& TL,
                 const double* pos, const md_nlist& nl, void* force, double* saved, double* vel,
                 double inv_mass, double half_dt, const DriftArgs& dr, long long* ev, int ev_cap,
                 double* partial, md_ctl_dev* ctl, hipStream_t st) {
@@ -783,24 +804,35 @@ void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_ta
   const size_t lds_f = ld ? (size_t)rows * MD_FTAB_W * sizeof(R) : 0;
 #define MD_EAM_LAUNCH(EVB, TL_, E_)                                                               \
   do {                                                                                         \
-    if constexpr (std::is_same<R, float>::value)                                               \
+    if constexpr (std::is_same<R, float>::value) {                                             \
+      if ((st_ = allow_big_lds((const void*)k_eam_density_f32<LANES, EVB, TL_, E_>, lds_d)))     \
+        return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f32<LANES, EVB, TL_, E_>), grid, block, \
                       lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
                       rc2, saved, partial, ev, ev_cap, ctl);                                   \
-    else                                                                                       \
+    } else {                                                                                   \
+      if ((st_ = allow_big_lds((const void*)k_eam_density_f64<LANES, EVB, TL_, E_>, lds_d)))     \
+        return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f64<LANES, EVB, TL_, E_>), grid, block, \
                       lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
                       rc2, saved, partial, ev, ev_cap, ctl);                                   \
-    if constexpr (std::is_same<R, float>::value)                                               \
+    }                                                                                          \
+    if constexpr (std::is_same<R, float>::value) {                                             \
+      if ((st_ = allow_big_lds((const void*)k_eam_force_f32<LANES, EVB, TL_, E_>, lds_f)))       \
+        return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f32<LANES, EVB, TL_, E_>), grid, block,     \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
                       rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);   \
-    else                                                                                       \
+    } else {                                                                                   \
+      if ((st_ = allow_big_lds((const void*)k_eam_force_f64<LANES, EVB, TL_, E_>, lds_f)))       \
+        return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f64<LANES, EVB, TL_, E_>), grid, block,     \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
                       rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);   \
+    }                                                                                          \
   } while (0)
   const bool big = md_big_list(nl, npad);
+  int st_ = MD_OK;
 #define MD_EAM_LAUNCH_E(EVB, TL_)                      \
   do {                                                 \
     if (big) MD_EAM_LAUNCH(EVB, TL_, uint64_t);        \
@@ -815,6 +847,7 @@ void launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_ta
   }
 #undef MD_EAM_LAUNCH_E
 #undef MD_EAM_LAUNCH
+  return MD_OK;
 }
 
 template <typename R, int LANES>
@@ -897,15 +930,19 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   double* partial = (double*)((char*)ws + WL.partial);
   hipStream_t st = (hipStream_t)stream;
   md_ctl_dev* c = (md_ctl_dev*)ctl;
+  int rc = MD_OK;
   if (prec == MD_FP32) {
-    MD_DISPATCH_LANES(nl->lanes, (launch_eam<float, L_>(*b, *p, (const char*)table, TL, pos, *nl,
-                                                        force, saved, vel, inv_mass, half_dt, dr,
-                                                        (long long*)ev, ev_cap, partial, c, st)));
+    MD_DISPATCH_LANES(nl->lanes, (rc = launch_eam<float, L_>(*b, *p, (const char*)table, TL, pos,
+                                                             *nl, force, saved, vel, inv_mass,
+                                                             half_dt, dr, (long long*)ev, ev_cap,
+                                                             partial, c, st)));
   } else {
-    MD_DISPATCH_LANES(nl->lanes, (launch_eam<double, L_>(*b, *p, (const char*)table, TL, pos, *nl,
-                                                         force, saved, vel, inv_mass, half_dt, dr,
-                                                         (long long*)ev, ev_cap, partial, c, st)));
+    MD_DISPATCH_LANES(nl->lanes, (rc = launch_eam<double, L_>(*b, *p, (const char*)table, TL, pos,
+                                                              *nl, force, saved, vel, inv_mass,
+                                                              half_dt, dr, (long long*)ev, ev_cap,
+                                                              partial, c, st)));
   }
+  if (rc != MD_OK) return rc;
   MD_LAUNCH_CHECK();
   return MD_OK;
 }
