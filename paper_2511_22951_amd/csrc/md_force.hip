@@ -166,6 +166,37 @@ __device__ __forceinline__ double4 load_rec(const double4* pos, int j) {
                                            (uint32_t)((uint32_t)j << 5));
 }
 
+// Neighbour records of the FP32 force pass: 16 bytes {u_x, u_y, u_z, F'} with the
+// coordinates in fixed point, u = rint((x - lo) 2^32 / span) mod 2^32 per axis.  On a
+// periodic axis span = L, so the wrapped 32-bit difference of two coordinates is the
+// minimum image (no branch, no rounding per pair); on other axes span = max(L, 4 r_ns),
+// and listed pairs (|d| < r_ns < span / 2) never alias, wherever the atoms are.  One
+// 16-byte load per neighbour instead of two for the FP64 record.
+struct FixBox {
+  double lo[3], scale[3];  // 2^32 / span
+  float inv[3];            // span / 2^32
+};
+__device__ __forceinline__ FixBox fix_box(const md_domain& D, double r_ns) {
+  FixBox f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double span = D.periodic[a] ? D.len[a] : fmax(D.len[a], 4.0 * r_ns);
+    f.lo[a] = D.lo[a];
+    f.scale[a] = 4294967296.0 / span;
+    f.inv[a] = (float)(span * 2.3283064365386963e-10);
+  }
+  return f;
+}
+__device__ __forceinline__ uint32_t fix_coord(double x, double lo, double scale) {
+  const double r = rint((x - lo) * scale);
+  const double q = floor(r * 2.3283064365386963e-10);  // r = q 2^32 + (r mod 2^32), exact
+  return (uint32_t)(r - q * 4294967296.0);
+}
+__device__ __forceinline__ uint4 load_rec16(const uint4* rec, int j) {
+  return *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(rec) +
+                                         (uint32_t)((uint32_t)j << 4));
+}
+
 // List entries are addressed with 32-bit byte offsets when the list holds fewer
 // than 2^30 entries (E = uint32_t), with 64-bit element offsets otherwise.
 __device__ __forceinline__ int load_idx(const int* neigh, uint32_t e) {
@@ -314,7 +345,7 @@ __device__ __forceinline__ void eam_density_body(
     const md_batch& b, double4* pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const R* __restrict__ rtab_g,
     const R* __restrict__ etab, const TabGeom& g, R rc2, double* saved, double* partial,
-    long long* ev, int ev_cap, md_ctl_dev* ctl) {
+    uint4* rec, long long* ev, int ev_cap, md_ctl_dev* ctl) {
   extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
   const R* rtab = TLDS ? stage_table<R, MD_RTAB_W>(rtab_g, pair_rows<R>(g), (R*)s_dyn) : rtab_g;
@@ -389,6 +420,12 @@ __device__ __forceinline__ void eam_density_body(
       const R F = ((row[3] * tt + row[2]) * tt + row[1]) * tt + row[0];
       const R F1 = (row[6] * tt + row[5]) * tt + row[4];
       store_fp<R>(pos, i, F1);
+      if (rec) {  // the force pass's record of this atom
+        const FixBox X = fix_box(b.domains[T.rep], b.r_ns);
+        const double4 p = load_xyz(pos, i);
+        rec[i] = make_uint4(fix_coord(p.x, X.lo[0], X.scale[0]), fix_coord(p.y, X.lo[1], X.scale[1]),
+                            fix_coord(p.z, X.lo[2], X.scale[2]), __float_as_uint((float)F1));
+      }
       if (saved) {
         const int n = b.n_atoms;
         saved[i] = (double)rho;
@@ -420,16 +457,16 @@ __device__ __forceinline__ void eam_density_body(
 #define MD_EAM_DENSITY_ARGS(R)                                                                 \
   md_batch b, double4 *pos, const int *__restrict__ neigh, const int *__restrict__ nneigh,   \
       int npad, const R *__restrict__ rtab_g, const R *__restrict__ etab, TabGeom g, R rc2,  \
-      double *saved, double *partial, long long *ev, int ev_cap, md_ctl_dev *ctl
+      double *saved, double *partial, uint4 *rec, long long *ev, int ev_cap, md_ctl_dev *ctl
 template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_density_f32(MD_EAM_DENSITY_ARGS(float)) {
   eam_density_body<float, LANES, EV, TLDS, 8, E>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
-                                           saved, partial, ev, ev_cap, ctl);
+                                           saved, partial, rec, ev, ev_cap, ctl);
 }
 template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_density_f64(MD_EAM_DENSITY_ARGS(double)) {
   eam_density_body<double, LANES, EV, TLDS, 4, E>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
-                                            saved, partial, ev, ev_cap, ctl);
+                                            saved, partial, nullptr, ev, ev_cap, ctl);
 }
 #undef MD_EAM_DENSITY_ARGS
 
@@ -484,7 +521,8 @@ __device__ __forceinline__ void eam_force_body(
     const md_batch& b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, const TabGeom& g,
     R rc2, R* force, double* vel, double inv_mass, double half_dt, const DriftArgs& dr,
-    const double* partial, long long* ev, int ev_cap, md_ctl_dev* ctl) {
+    const double* partial, const uint4* rec, long long* ev, int ev_cap, md_ctl_dev* ctl) {
+  constexpr bool FP32 = std::is_same<R, float>::value;
   constexpr int U = 4;  // (8 in flight measured slower here: the gathers contend)
   extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
@@ -505,12 +543,47 @@ __device__ __forceinline__ void eam_force_body(
     }
   }
   const bool wimg = __any(raw & MD_NN_IMG);
-  if (i >= 0) {
+  if constexpr (FP32) {
+    if (i >= 0) {
+      // separations from the fixed-point records (the minimum image by 32-bit wrap-around);
+      // the virial is accumulated per pair, W = 1/2 sum_ij r_ij (x) f_ij
+      const FixBox X = fix_box(b.domains[T.rep], b.r_ns);
+      const uint4 ri = rec[i];
+      const float fpi = __uint_as_float(ri.w);
+      const float qih = (float)g.q_inv_h, qloh = (float)(g.q_lo * g.q_inv_h);
+      const E e0 = (E)i * LANES + S.l, stride = (E)npad * LANES;
+      auto pair = [&](uint4 q, bool valid) {
+        const float x = (float)(int)(q.x - ri.x) * X.inv[0];
+        const float y = (float)(int)(q.y - ri.y) * X.inv[1];
+        const float z = (float)(int)(q.z - ri.z) * X.inv[2];
+        const float r2 = x * x + y * y + z * z;
+        const bool in = valid && r2 < rc2;  // branch-free: pairs beyond r_c are masked
+        // s = [phi'(r) + (F'_i + F'_j) rho'(r)] / r; the force on i from j is s (r_j - r_i)
+        float tt;
+        const float* row = ftab + qtab_index(r2, qih, qloh, tt) * MD_FTAB_W;
+        const float s0 = cubic(row, tt) + (fpi + __uint_as_float(q.w)) * cubic(row + 4, tt);
+        const float sv = in ? s0 : 0.0f;
+        const float px = sv * x, py = sv * y, pz = sv * z;
+        fx += px;
+        fy += py;
+        fz += pz;
+        if (EV) {  // r_ij (x) f_ij with r_ij = -(x, y, z)
+          w[0] -= x * px;
+          w[1] -= y * py;
+          w[2] -= z * pz;
+          w[3] -= x * py;
+          w[4] -= x * pz;
+          w[5] -= y * pz;
+        }
+      };
+      visit_list_pipe<LANES, U>(neigh, e0, stride, S.l, nn, i,
+                                [&](int j) { return load_rec16(rec, j); }, pair);
+    }
+  } else if (i >= 0) {
     const Img D(&b.domains[T.rep]);
     const double4 pi = pos[i];
     const R fpi = load_fp<R>(pi.w);
     const R rih = (R)g.r_inv_h, rloh = (R)(g.r_lo * g.r_inv_h);
-    const float qih = (float)g.q_inv_h, qloh = (float)(g.q_lo * g.q_inv_h);
     const E e0 = (E)i * LANES + S.l, stride = (E)npad * LANES;
     auto run = [&](auto img_tag) {
       constexpr bool IMG = decltype(img_tag)::value;
@@ -522,22 +595,15 @@ __device__ __forceinline__ void eam_force_body(
         const bool in = valid && r2 < rc2;  // branch-free: pairs beyond r_c are masked
         // s = [phi'(r) + (F'_i + F'_j) rho'(r)] / r; the force on i from j is s (r_j - r_i).
         // (Pairs below the table are flagged by the density pass, which sees the same r.)
-        R s0;
-        if constexpr (std::is_same<R, float>::value) {
-          float tt;
-          const float* row = ftab + qtab_index(r2, qih, qloh, tt) * MD_FTAB_W;
-          s0 = cubic(row, tt) + (fpi + load_fp<R>(pj.w)) * cubic(row + 4, tt);
-        } else {
-          const R rinv = rsqrt_r<R>(r2);
-          const R r = r2 * rinv;
-          R tt;
-          bool below = false;
-          const int k = tab_index_masked<R>(r, rih, rloh, g.nr, in, tt, below);
-          const R* row = ftab + k * MD_FTAB_W;
-          const R dphi = (row[2] * tt + row[1]) * tt + row[0];
-          const R drho = (row[5] * tt + row[4]) * tt + row[3];
-          s0 = (dphi + (fpi + load_fp<R>(pj.w)) * drho) * rinv;
-        }
+        const R rinv = rsqrt_r<R>(r2);
+        const R r = r2 * rinv;
+        R tt;
+        bool below = false;
+        const int k = tab_index_masked<R>(r, rih, rloh, g.nr, in, tt, below);
+        const R* row = ftab + k * MD_FTAB_W;
+        const R dphi = (row[2] * tt + row[1]) * tt + row[0];
+        const R drho = (row[5] * tt + row[4]) * tt + row[3];
+        const R s0 = (dphi + (fpi + load_fp<R>(pj.w)) * drho) * rinv;
         const R s = in ? s0 : (R)0;
         const R px = s * x, py = s * y, pz = s * z;
         fx += px;
@@ -576,7 +642,7 @@ __device__ __forceinline__ void eam_force_body(
     } else {
       acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
     }
-    if (EV) {
+    if (EV && !FP32) {
       // x_i (x) F_i: the atom's position with its total force (FP64)
       const double4 pi = load_xyz(pos, i);
       const double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
@@ -613,17 +679,17 @@ __device__ __forceinline__ void eam_force_body(
   md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,                  \
       const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, TabGeom g, R rc2, \
       R *force, double *vel, double inv_mass, double half_dt, DriftArgs dr,                     \
-      const double *partial, long long *ev, int ev_cap, md_ctl_dev *ctl
+      const double *partial, const uint4 *rec, long long *ev, int ev_cap, md_ctl_dev *ctl
 template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_force_f32(
     MD_EAM_FORCE_ARGS(float)) {
   eam_force_body<float, LANES, EV, TLDS, E>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
-                                         inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);
+                                         inv_mass, half_dt, dr, partial, rec, ev, ev_cap, ctl);
 }
 template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_force_f64(MD_EAM_FORCE_ARGS(double)) {
   eam_force_body<double, LANES, EV, TLDS, E>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
-                                          inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);
+                                          inv_mass, half_dt, dr, partial, nullptr, ev, ev_cap, ctl);
 }
 #undef MD_EAM_FORCE_ARGS
 
@@ -780,7 +846,8 @@ template <typename R, int LANES>
 int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_table_layout& TL,
                 const double* pos, const md_nlist& nl, void* force, double* saved, double* vel,
                 double inv_mass, double half_dt, const DriftArgs& dr, long long* ev, int ev_cap,
-                double* partial, md_ctl_dev* ctl, hipStream_t st) {
+                double* partial, uint4* rec_ws, md_ctl_dev* ctl, hipStream_t st) {
+  uint4* rec = std::is_same<R, float>::value ? rec_ws : nullptr;  // FP32: fixed-point records
   TabGeom g;
   g.r_lo = p.rho.x_lo;
   g.r_inv_h = 1.0 / p.rho.h;
@@ -809,26 +876,28 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
         return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f32<LANES, EVB, TL_, E_>), grid, block, \
                       lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
-                      rc2, saved, partial, ev, ev_cap, ctl);                                   \
+                      rc2, saved, partial, rec, ev, ev_cap, ctl);                              \
     } else {                                                                                   \
       if ((st_ = allow_big_lds((const void*)k_eam_density_f64<LANES, EVB, TL_, E_>, lds_d)))     \
         return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f64<LANES, EVB, TL_, E_>), grid, block, \
                       lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
-                      rc2, saved, partial, ev, ev_cap, ctl);                                   \
+                      rc2, saved, partial, rec, ev, ev_cap, ctl);                              \
     }                                                                                          \
     if constexpr (std::is_same<R, float>::value) {                                             \
       if ((st_ = allow_big_lds((const void*)k_eam_force_f32<LANES, EVB, TL_, E_>, lds_f)))       \
         return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f32<LANES, EVB, TL_, E_>), grid, block,     \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
-                      rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);   \
+                      rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, rec, ev, ev_cap,    \
+                      ctl);                                                                    \
     } else {                                                                                   \
       if ((st_ = allow_big_lds((const void*)k_eam_force_f64<LANES, EVB, TL_, E_>, lds_f)))       \
         return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f64<LANES, EVB, TL_, E_>), grid, block,     \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
-                      rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, ev, ev_cap, ctl);   \
+                      rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, rec, ev, ev_cap,    \
+                      ctl);                                                                    \
     }                                                                                          \
   } while (0)
   const bool big = md_big_list(nl, npad);
@@ -928,6 +997,7 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   const md_table_layout TL = md_table_plan(p, prec);
   const md_ws_layout WL = md_ws_plan(b);
   double* partial = (double*)((char*)ws + WL.partial);
+  uint4* rec = (uint4*)((char*)ws + WL.rec);
   hipStream_t st = (hipStream_t)stream;
   md_ctl_dev* c = (md_ctl_dev*)ctl;
   int rc = MD_OK;
@@ -935,12 +1005,12 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
     MD_DISPATCH_LANES(nl->lanes, (rc = launch_eam<float, L_>(*b, *p, (const char*)table, TL, pos,
                                                              *nl, force, saved, vel, inv_mass,
                                                              half_dt, dr, (long long*)ev, ev_cap,
-                                                             partial, c, st)));
+                                                             partial, rec, c, st)));
   } else {
     MD_DISPATCH_LANES(nl->lanes, (rc = launch_eam<double, L_>(*b, *p, (const char*)table, TL, pos,
                                                               *nl, force, saved, vel, inv_mass,
                                                               half_dt, dr, (long long*)ev, ev_cap,
-                                                              partial, c, st)));
+                                                              partial, rec, c, st)));
   }
   if (rc != MD_OK) return rc;
   MD_LAUNCH_CHECK();

@@ -62,7 +62,7 @@ __device__ __forceinline__ void md_step_bookkeeping(md_ctl_dev* ctl) {
 
 // Offsets of the workspace regions (bytes, 256-aligned).
 struct md_ws_layout {
-  size_t cell_of, rank, src, sid, counts, scan, pos_s, vel_s, id_s, partial, total;
+  size_t cell_of, rank, src, sid, counts, scan, pos_s, vel_s, id_s, partial, rec, total;
 };
 
 // Blocks of the cell-histogram scan (one segment of cells each).
@@ -91,6 +91,7 @@ static inline md_ws_layout md_ws_plan(const md_batch* b) {
   L.vel_s = o;   o = md_align256(o + 24 * n);
   L.id_s = o;    o = md_align256(o + 4 * n);
   L.partial = o; o = md_align256(o + 8 * MD_EV_LEN * (size_t)b->n_tiles);
+  L.rec = o;     o = md_align256(o + 16 * n);  // FP32 EAM: fixed-point neighbour records
   L.total = o;
   return L;
 }
