@@ -332,6 +332,24 @@ int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec, const v
                   long long* ev, int ev_cap, void* ws,
                   void* ctl, void* stream);
 
+/* md_eam_forces without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as md_eam_forces, minus ws; the scratch
+ * (tile energy partials and the FP32 neighbour records) lives in a static device array of
+ * the library, MD_NOALLOC_MAX_TILES * 64 + MD_NOALLOC_MAX_ATOMS * 16 bytes (18 MiB), one
+ * copy per GPU, held until the process ends.  Batches with more than MD_NOALLOC_MAX_ATOMS
+ * atoms or MD_NOALLOC_MAX_TILES tiles return MD_ERR_WORKSPACE.  The call allocates nothing;
+ * its first call on a device looks up that device's copy of the array (hipGetSymbolAddress).
+ * All calls on one GPU share the array: calls that overlap on one GPU (on different streams
+ * or from different threads without ordering) race. */
+#define MD_NOALLOC_MAX_ATOMS (1 << 20)
+#define MD_NOALLOC_MAX_TILES 32768
+int md_eam_forces_noalloc(const md_batch* b, const md_eam* p, md_precision prec,
+                          const void* table, const double* pos, const md_nlist* nl, void* force,
+                          double* saved, double* vel, double inv_mass, double half_dt,
+                          const md_drift* drift, long long* ev, int ev_cap, void* ctl,
+                          void* stream);
+
 /* Velocity Verlet (Sec. 1.5).  MD_KICK_DRIFT: the Langevin update if lang is not
  * NULL (md_langevin), then v += half_dt f/m; x += dt v; walls at t = (step + 1) dt;
  * per-block maxima of |x - pos_ref|^2 are kept for the rebuild decision (compared

@@ -19,6 +19,9 @@ FLAG_NEIGH_OVERFLOW, FLAG_TABLE_RANGE, FLAG_WALL, FLAG_NONFINITE, FLAG_STALE_LIS
 MD_ERR_ARG = -1
 MD_DRIFT_MAX_BLOCKS = 32768
 MD_ERR_STALE_LIST = -9
+MD_ERR_WORKSPACE = -8
+MD_NOALLOC_MAX_ATOMS = 1 << 20
+MD_NOALLOC_MAX_TILES = 32768
 
 
 class MDError(RuntimeError):
@@ -122,6 +125,8 @@ _SIGS = {
                           _vp, _i, _vp, _vp, _vp]),
     "md_eam_forces": (_i, [_P(Batch), _P(EAM), _i, _vp, _vp, _P(NList), _vp, _vp, _vp, _d, _d,
                            _P(Drift), _vp, _i, _vp, _vp, _vp]),
+    "md_eam_forces_noalloc": (_i, [_P(Batch), _P(EAM), _i, _vp, _vp, _P(NList), _vp, _vp, _vp,
+                                   _d, _d, _P(Drift), _vp, _i, _vp, _vp]),
     "md_verlet_step": (_i, [_P(Batch), _i, _d, _vp, _vp, _vp, _i, _d, _P(Walls), _P(Langevin),
                             _vp, _d, _vp, _vp]),
     "md_eam_backward": (_i, [_P(Batch), _P(EAM), _i, _vp, _P(NList), _vp, _vp, _vp, _vp, _vp,

@@ -1048,12 +1048,16 @@ static int drift_load(const md_batch* b, const md_nlist* nl, const double* pos, 
   return MD_OK;
 }
 
-extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec,
-                             const void* table, const double* pos, const md_nlist* nl,
-                             void* force, double* saved, double* vel, double inv_mass,
-                             double half_dt, const md_drift* drift, long long* ev, int ev_cap,
-                             void* ws, void* ctl, void* stream) {
-  if (!md_batch_ok(b) || !md_eam_ok(p) || !table || !pos || !nlist_ok(nl) || !force || !ws || !ctl)
+// md_eam_forces with its scratch given as pointers: the tiles' energy partials
+// (8 MD_EV_LEN doubles per tile) and, in FP32, the fixed-point neighbour records (16 bytes
+// per atom).  ws_ok: the caller has a workspace or scratch to pass.
+static int eam_forces(const md_batch* b, const md_eam* p, md_precision prec, const void* table,
+                      const double* pos, const md_nlist* nl, void* force, double* saved,
+                      double* vel, double inv_mass, double half_dt, const md_drift* drift,
+                      long long* ev, int ev_cap, double* partial, uint4* rec, bool ws_ok,
+                      void* ctl, void* stream) {
+  if (!md_batch_ok(b) || !md_eam_ok(p) || !table || !pos || !nlist_ok(nl) || !force || !ws_ok ||
+      !ctl)
     return MD_ERR_ARG;
   if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
   if (ev && ev_cap < 1) return MD_ERR_ARG;
@@ -1064,9 +1068,6 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   if (drift_load(b, nl, pos, vel, half_dt, drift, &dr) != MD_OK) return MD_ERR_ARG;
   if (b->n_atoms == 0 || b->n_tiles == 0) return MD_OK;
   const md_table_layout TL = md_table_plan(p, prec);
-  const md_ws_layout WL = md_ws_plan(b);
-  double* partial = (double*)((char*)ws + WL.partial);
-  uint4* rec = (uint4*)((char*)ws + WL.rec);
   hipStream_t st = (hipStream_t)stream;
   md_ctl_dev* c = (md_ctl_dev*)ctl;
   int rc = MD_OK;
@@ -1084,6 +1085,69 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   if (rc != MD_OK) return rc;
   MD_LAUNCH_CHECK();
   return MD_OK;
+}
+
+extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision prec,
+                             const void* table, const double* pos, const md_nlist* nl,
+                             void* force, double* saved, double* vel, double inv_mass,
+                             double half_dt, const md_drift* drift, long long* ev, int ev_cap,
+                             void* ws, void* ctl, void* stream) {
+  double* partial = nullptr;
+  uint4* rec = nullptr;
+  if (ws && b && b->n_atoms >= 0 && b->n_tiles >= 0) {
+    const md_ws_layout WL = md_ws_plan(b);
+    partial = (double*)((char*)ws + WL.partial);
+    rec = (uint4*)((char*)ws + WL.rec);
+  }
+  return eam_forces(b, p, prec, table, pos, nl, force, saved, vel, inv_mass, half_dt, drift, ev,
+                    ev_cap, partial, rec, ws != nullptr, ctl, stream);
+}
+
+// ---------------------------------------------------------------------------
+// md_eam_forces_noalloc: the same passes with their scratch in a static device array.
+// Layout: tile energy partials (MD_NOALLOC_MAX_TILES tiles), then the FP32 records
+// (MD_NOALLOC_MAX_ATOMS atoms).  Every call on a device uses that device's one copy;
+// nothing in it needs to start at zero (each pass writes what the next reads).
+// ---------------------------------------------------------------------------
+#define MD_NOALLOC_PARTIAL_BYTES ((size_t)MD_NOALLOC_MAX_TILES * MD_EV_LEN * sizeof(double))
+#define MD_NOALLOC_REC_BYTES ((size_t)MD_NOALLOC_MAX_ATOMS * sizeof(uint4))
+static __device__ __align__(256) unsigned char scratch[MD_NOALLOC_PARTIAL_BYTES +
+                                                       MD_NOALLOC_REC_BYTES];
+
+#define MD_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[MD_MAX_DEVICES];  // device address of `scratch` on each device
+
+// The current device's address of `scratch`, looked up once per device (with that device
+// current).  The array's name in host code is a host-side stand-in, never a device address.
+static int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MD_MAX_DEVICES) return MD_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MD_ERR_HIP;
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return MD_OK;
+}
+
+extern "C" int md_eam_forces_noalloc(const md_batch* b, const md_eam* p, md_precision prec,
+                                     const void* table, const double* pos, const md_nlist* nl,
+                                     void* force, double* saved, double* vel, double inv_mass,
+                                     double half_dt, const md_drift* drift, long long* ev,
+                                     int ev_cap, void* ctl, void* stream) {
+  if (!md_batch_ok(b)) return MD_ERR_ARG;
+  if (b->n_atoms > MD_NOALLOC_MAX_ATOMS || b->n_tiles > MD_NOALLOC_MAX_TILES)
+    return MD_ERR_WORKSPACE;
+  void* base = nullptr;
+  const int st = scratch_address(&base);
+  if (st != MD_OK) return st;
+  double* partial = (double*)base;
+  uint4* rec = (uint4*)((char*)base + MD_NOALLOC_PARTIAL_BYTES);
+  return eam_forces(b, p, prec, table, pos, nl, force, saved, vel, inv_mass, half_dt, drift, ev,
+                    ev_cap, partial, rec, true, ctl, stream);
 }
 
 extern "C" int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec,

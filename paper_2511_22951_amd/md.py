@@ -300,6 +300,20 @@ def md_eam_forces(st: State, pot: EAMPotential, nl: NeighborList, table=None, sa
           "md_eam_forces")
 
 
+def md_eam_forces_noalloc(st: State, pot: EAMPotential, nl: NeighborList, table=None,
+                          saved=None, inv_mass=0.0, half_dt=0.0, kick=False, ev=None, ev_cap=1,
+                          drift=None, stream=None):
+    """md_eam_forces with the library's static scratch instead of the state's workspace."""
+    table = pot.table(st.precision) if table is None else table
+    vel = st.vel if kick else None
+    check(N.lib().md_eam_forces_noalloc(C.byref(st.plan.c), C.byref(pot.c), st.precision,
+                                        _ptr(table), _ptr(st.pos), C.byref(nl.c), _ptr(st.force),
+                                        _ptr(saved), _ptr(vel), float(inv_mass), float(half_dt),
+                                        C.byref(drift) if drift is not None else None, _ptr(ev),
+                                        int(ev_cap), _ptr(st.ctl), _stream(stream)),
+          "md_eam_forces_noalloc")
+
+
 def langevin_params(st: State, thermostat):
     """md_langevin from {"seed": int, "axis": 0-2, "regions": [{"lo", "hi", "T", "gamma",
     "u": (ux, uy, uz)}, ...]} (lo/hi default to an unbounded slab, u to zero)."""

@@ -89,3 +89,15 @@ def test_batch_plan_tiles_never_straddle_boxes(lib):
         d = doms[T.rep]
         assert d.atom_off <= T.first and T.first + T.count <= d.atom_off + d.n_atoms
     assert sum(doms[r].n_tiles for r in range(n)) == nt.value
+
+
+def test_noalloc_entry_point_rejects_oversize_batches(lib):
+    """md_eam_forces_noalloc refuses batches beyond its static scratch with MD_ERR_WORKSPACE,
+    on the host, before any device work."""
+    from paper_2511_22951_amd import _native as N
+    dummy = C.c_void_p(0x1000)
+    for n_atoms, n_tiles in ((N.MD_NOALLOC_MAX_ATOMS + 1, 16385), (1000, N.MD_NOALLOC_MAX_TILES + 1)):
+        b = N.Batch(1, n_atoms, 8, n_tiles, 64, 0, 5.8, dummy, dummy)
+        st = lib.md_eam_forces_noalloc(C.byref(b), None, 1, None, None, None, None, None, None,
+                                       0.0, 0.0, None, None, 1, None, None)
+        assert st == N.MD_ERR_WORKSPACE
