@@ -827,11 +827,11 @@ def bench_bpnn(args):
     print(json.dumps(out), flush=True)
 
 
-def _static_batch(reps, prec, lanes, max_neigh=128):
+def _static_batch(reps, prec, lanes, max_neigh=128, block=0):
     from paper_2511_22951_amd import md
     plan = md.Plan([r.box for r in reps], [len(r.pos) for r in reps], 5.8)
     st = md.State(plan, np.concatenate([r.pos for r in reps]), None, prec)
-    nl = md.NeighborList(plan.n_atoms, max_neigh, lanes)
+    nl = md.NeighborList(plan.n_atoms, max_neigh, lanes, block=block)
     md.md_bin_cells(st)
     md.md_build_neighbors(st, nl)
     return plan, st, nl
@@ -857,28 +857,40 @@ def bench_cold_curve(args):
     for name, prec in (("fp32", N.MD_FP32), ("fp64", N.MD_FP64)):
         table = pot.table(prec)
 
-        def batched(lanes):
-            plan, st, nl = _static_batch(reps, prec, lanes)
+        def batched(shape):
+            plan, st, nl = _static_batch(reps, prec, shape[0], block=shape[1])
             ev = md.ev_buffer(1, len(reps))
             fn = lambda: md.md_eam_forces(st, pot, nl, table=table, ev=ev)
             return fn, (plan, st, nl, ev)
 
-        def timed(lanes):
-            fn, keep = batched(lanes)
+        def timed(shape):
+            fn, keep = batched(shape)
             replay, g = _replay_graph(fn)
             return _gpu_time(replay, 10) / 10
 
-        lanes = args.lanes or tune.pick(("cold_curve64", name), (1, 2, 4, 8), timed)
-        fn, (plan, st, nl, ev) = batched(lanes)
+        # launch shape: (lanes per atom, workgroup size) from the project's tuner, beside the
+        # fixed default shape (4 lanes, 1024 threads)
+        fixed = (4, 1024)
+        shape = (args.lanes, 1024) if args.lanes else tune.pick(
+            ("cold_curve64", name, "shape"), tune.shapes(prec), timed)
+        fn, (plan, st, nl, ev) = batched(shape)
         replay, g = _replay_graph(fn)
         t_b = _gpu_time(replay, evals) / evals
+        if shape != fixed:
+            fn_f, keep_f = batched(fixed)
+            replay_f, g_f = _replay_graph(fn_f)
+            t_fixed = _gpu_time(replay_f, evals) / evals
+            del g_f, keep_f
+        else:
+            t_fixed = t_b
+        lanes = shape[0]
         st.check_flags()
         e = md.ev_values(ev)[0]
         e_gpu[name] = (e[:, 0], st)
         # per-replica loop: one plan/state/list per replica, 64 launches per evaluation
         singles = []
         for r in reps:
-            p1, s1, n1 = _static_batch([r], prec, lanes)
+            p1, s1, n1 = _static_batch([r], prec, lanes, block=shape[1])
             singles.append((s1, n1, md.ev_buffer(1, 1)))
 
         def loop():
@@ -891,6 +903,9 @@ def bench_cold_curve(args):
                      "replica_evals_per_s": reps_per_eval / (t_b * 1e-3),
                      "atom_evals_per_s": n_tot / (t_b * 1e-3),
                      "batched_speedup_over_loop": t_l / t_b, "lanes": lanes,
+                     "tuned_shape": {"lanes": shape[0], "block": shape[1]},
+                     "ms_per_eval_fixed_shape_4x1024": t_fixed,
+                     "tuned_speedup_over_fixed_shape": t_fixed / t_b,
                      "max_abs_force": float(np.max(np.abs(st.forces())))}
         del g, g_l
     per_atom = np.array([len(r.pos) for r in reps], np.float64)

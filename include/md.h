@@ -129,6 +129,10 @@ typedef struct md_nlist {
                    the atom's 3x3x3 cell block crosses a periodic boundary */
   int max_neigh;/* multiple of lanes */
   int lanes;    /* 1, 2, 4, 8 or 16 */
+  int block;    /* threads per workgroup of the force passes (the atoms one workgroup takes,
+                   block / lanes, are its task): 0 (= 1024), 256, 512 or 1024, at least
+                   64 * lanes; MD_ERR_ARG otherwise.  A launch-shape choice only: results
+                   do not depend on it beyond the rounding order of the per-box records. */
 } md_nlist;
 
 #define MD_NN_IMG (1 << 30)

@@ -54,7 +54,7 @@ class Batch(C.Structure):
 
 class NList(C.Structure):
     _fields_ = [("neigh", C.c_void_p), ("nneigh", C.c_void_p), ("max_neigh", C.c_int),
-                ("lanes", C.c_int)]
+                ("lanes", C.c_int), ("block", C.c_int)]
 
 
 class Spline(C.Structure):

@@ -115,11 +115,14 @@ __device__ __forceinline__ float cubic(const float* a, float t) {
   return ((a[3] * t + a[2]) * t + a[1]) * t + a[0];
 }
 
-// Blocks of the force passes: 1024 threads = TPB work tiles of 64 atoms x LANES lanes.
+// Blocks of the force passes: up to 1024 threads (md_nlist.block: 256, 512 or 1024, default
+// 1024), each block TPB work tiles of 64 atoms x LANES lanes.
 constexpr int FBLOCK = 1024;
-template <int LANES> struct Shape {
-  static constexpr int TPB = FBLOCK / (64 * LANES);
-};
+template <int LANES>
+__device__ __forceinline__ int tiles_per_block() {
+  return __builtin_amdgcn_readfirstlane((int)blockDim.x / (64 * LANES));
+}
+static inline int block_threads(const md_nlist& nl) { return nl.block ? nl.block : FBLOCK; }
 
 // Where a thread sits: its tile (-1 if none), its atom slot and lane.
 struct Slot {
@@ -127,7 +130,7 @@ struct Slot {
 };
 template <int LANES>
 __device__ __forceinline__ Slot force_slot(int n_tiles) {
-  constexpr int TPB = Shape<LANES>::TPB;
+  const int TPB = tiles_per_block<LANES>();
   const int nlb = (n_tiles + TPB - 1) / TPB;
   const int lb = md_remap_block(nlb);
   Slot s;
@@ -323,8 +326,7 @@ __device__ __forceinline__ long long to_fixed(double v) {
 
 // Add a block's per-tile sums (tsum[g][k], g < TPB) into the record slot: tiles
 // of one box are combined first, then one atomic per (box, component).
-template <int TPB>
-__device__ __forceinline__ void accumulate_record(const md_batch& b, int lb, int nlb,
+__device__ __forceinline__ void accumulate_record(const md_batch& b, int TPB, int lb, int nlb,
                                                   const double* tsum, long long* slot) {
   const int k = threadIdx.x;
   if (k >= MD_EV_LEN || lb >= nlb) return;
@@ -508,7 +510,7 @@ __device__ __forceinline__ void eam_density_body(
     double res;
     int gg, kk;
     if (md_group_waves_sum<1>(v, LANES, sh, res, gg, kk)) {
-      constexpr int TPB = Shape<LANES>::TPB;
+      const int TPB = tiles_per_block<LANES>();
       const int nlb = (b.n_tiles + TPB - 1) / TPB;
       const int lb = md_remap_block(nlb);
       const int t = lb * TPB + gg;
@@ -723,7 +725,7 @@ __device__ __forceinline__ void eam_force_body(
   if (EV) {
     double res;
     int gg, kk;
-    constexpr int TPB = Shape<LANES>::TPB;
+    const int TPB = tiles_per_block<LANES>();
     const int nlb = (b.n_tiles + TPB - 1) / TPB;
     const int lb = md_remap_block(nlb);
     if (md_group_waves_sum<7>(acc, LANES, sh, res, gg, kk)) {
@@ -733,7 +735,7 @@ __device__ __forceinline__ void eam_force_body(
       if (kk == 0) tsum[gg * MD_EV_LEN] = (lb < nlb && t < b.n_tiles) ? partial[(size_t)t * MD_EV_LEN] : 0.0;
     }
     __syncthreads();
-    accumulate_record<TPB>(b, lb, nlb, tsum, ev + (size_t)(ctl->step % ev_cap) * b.n_rep * MD_EV_LEN);
+    accumulate_record(b, TPB, lb, nlb, tsum, ev + (size_t)(ctl->step % ev_cap) * b.n_rep * MD_EV_LEN);
   }
   if (dr.pos_out) md_publish_dmax(d2max, bad, dr.thr2, ctl);
 }
@@ -856,12 +858,12 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
     for (int k = 0; k < 6; ++k) acc[1 + k] = 0.5 * (double)w[k];
     double res;
     int gg, kk;
-    constexpr int TPB = Shape<LANES>::TPB;
+    const int TPB = tiles_per_block<LANES>();
     const int nlb = (b.n_tiles + TPB - 1) / TPB;
     const int lb = md_remap_block(nlb);
     if (md_group_waves_sum<8>(acc, LANES, sh, res, gg, kk)) tsum[gg * MD_EV_LEN + kk] = res;
     __syncthreads();
-    accumulate_record<TPB>(b, lb, nlb, tsum,
+    accumulate_record(b, TPB, lb, nlb, tsum,
                            ev + (size_t)(ctl->step % ev_cap) * b.n_rep * MD_EV_LEN);
   }
   if (dr.pos_out) md_publish_dmax(d2max, bad, dr.thr2, ctl);
@@ -874,6 +876,8 @@ bool nlist_ok(const md_nlist* nl) {
   if (!nl || !nl->neigh || !nl->nneigh) return false;
   const int L = nl->lanes;
   if (L != 1 && L != 2 && L != 4 && L != 8 && L != 16) return false;
+  const int B = block_threads(*nl);
+  if ((B != 256 && B != 512 && B != 1024) || B < 64 * L) return false;
   return nl->max_neigh >= L && nl->max_neigh % L == 0;
 }
 
@@ -925,8 +929,8 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
   g.q_lo = qg.q_lo;
   g.q_inv_h = 1.0 / qg.h;
   const R rc2 = (R)(p.r_cut * p.r_cut);
-  constexpr int TPB = Shape<LANES>::TPB;
-  const dim3 grid(md_grid_blocks((b.n_tiles + TPB - 1) / TPB)), block(FBLOCK);
+  const int bt = block_threads(nl), TPB = bt / (64 * LANES);
+  const dim3 grid(md_grid_blocks((b.n_tiles + TPB - 1) / TPB)), block(bt);
   const int npad = md_npad(b.n_atoms);
   const R* rtab = (const R*)(tab + TL.rtab);
   const R* ftab = (const R*)(tab + TL.ftab);
@@ -999,8 +1003,8 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
   const double src6 = pow(p.sigma / p.r_cut, 6.0);
   c.ucut = 4.0 * p.eps * (src6 * src6 - src6);
   const R rc2 = (R)(p.r_cut * p.r_cut);
-  constexpr int TPB = Shape<LANES>::TPB;
-  const dim3 grid(md_grid_blocks((b.n_tiles + TPB - 1) / TPB)), block(FBLOCK);
+  const int bt = block_threads(nl), TPB = bt / (64 * LANES);
+  const dim3 grid(md_grid_blocks((b.n_tiles + TPB - 1) / TPB)), block(bt);
   const int npad = md_npad(b.n_atoms);
   const bool big = md_big_list(nl, npad);
 #define MD_LJ_LAUNCH(EVB, E_)                                                                  \
@@ -1043,7 +1047,7 @@ static int drift_load(const md_batch* b, const md_nlist* nl, const double* pos, 
   dr->pos_ref = drift->pos_ref;
   dr->dt = drift->dt;
   dr->thr2 = drift->half_skin < 0.0 ? -1.0 : drift->half_skin * drift->half_skin;
-  const int tpb = FBLOCK / (64 * nl->lanes);
+  const int tpb = block_threads(*nl) / (64 * nl->lanes);
   if (md_grid_blocks((b->n_tiles + tpb - 1) / tpb) > MD_DMAX_SLOTS) return MD_ERR_ARG;
   return MD_OK;
 }

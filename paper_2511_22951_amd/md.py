@@ -99,14 +99,21 @@ class Plan:
 class NeighborList:
     """Padded strided ELL list (md_nlist) for `lanes` lanes per atom."""
 
-    def __init__(self, n_atoms, max_neigh=128, lanes=4, device="cuda"):
+    def __init__(self, n_atoms, max_neigh=128, lanes=4, device="cuda", block=0):
+        """block: threads per workgroup of the force passes (0: the library default, 1024)."""
         if max_neigh % lanes:
             max_neigh += lanes - max_neigh % lanes
-        self.n, self.max_neigh, self.lanes = n_atoms, max_neigh, lanes
+        self.n, self.max_neigh, self.lanes, self.block = n_atoms, max_neigh, lanes, int(block)
         self.npad = (n_atoms + 63) // 64 * 64
         self.neigh = torch.zeros(max_neigh * self.npad, dtype=torch.int32, device=device)
         self.nneigh = torch.zeros(max(1, n_atoms), dtype=torch.int32, device=device)
-        self.c = N.NList(self.neigh.data_ptr(), self.nneigh.data_ptr(), max_neigh, lanes)
+        self.c = N.NList(self.neigh.data_ptr(), self.nneigh.data_ptr(), max_neigh, lanes,
+                         self.block)
+
+    def set_block(self, block):
+        """Change the force passes' workgroup size (a launch-shape choice)."""
+        self.block = int(block)
+        self.c.block = self.block
 
     def lengths(self):
         """List lengths (the image flag masked off)."""

@@ -60,18 +60,19 @@ def timed_graph_plan(n_steps, rebuild_every, fused, graph_steps):
     return G, n_steps // G, n_steps % G
 
 
-def fused_grid_fits(n_tiles, lanes):
-    """Whether a force pass of `lanes` lanes per atom over n_tiles tiles (16 / lanes tiles per
-    1024-thread block, the grid rounded up to a multiple of 8) fits the displacement slots
-    the fused kick-drift publishes into."""
-    tpb = 16 // lanes
+def fused_grid_fits(n_tiles, lanes, block=0):
+    """Whether a force pass of `lanes` lanes per atom over n_tiles tiles (block / (64 lanes)
+    tiles per block of `block` threads, default 1024; the grid rounded up to a multiple of 8)
+    fits the displacement slots the fused kick-drift publishes into."""
+    tpb = max(1, (block or 1024) // (64 * lanes))
     blocks = (n_tiles + tpb - 1) // tpb
     return (blocks + 7) // 8 * 8 <= N.MD_DRIFT_MAX_BLOCKS
 
 
 class Simulation:
     def __init__(self, system, precision=N.MD_FP64, lanes=4, max_neigh=128, ev_cap=1024,
-                 device="cuda", table=None, rebuild_every=0, fused=False, thermostat=None):
+                 device="cuda", table=None, rebuild_every=0, fused=False, thermostat=None,
+                 block=0):
         self.sys = system
         # the Langevin update runs in the kick-drift kernel, so it is not fused
         self.fused = bool(fused) and system.potential in ("eam", "lj") and thermostat is None
@@ -89,8 +90,8 @@ class Simulation:
         self.r_ns = r_cut + system.skin
         self.plan = md.Plan([system.box], [system.pos.shape[0]], self.r_ns, device)
         self.state = md.State(self.plan, system.pos, system.vel, precision)
-        self.nl = md.NeighborList(self.plan.n_atoms, max_neigh, lanes, device)
-        if self.fused and not fused_grid_fits(self.plan.n_tiles, lanes):
+        self.nl = md.NeighborList(self.plan.n_atoms, max_neigh, lanes, device, block=block)
+        if self.fused and not fused_grid_fits(self.plan.n_tiles, lanes, block):
             raise ValueError("fused kick-drift: %d lanes per atom over %d atoms exceed the "
                              "force pass's %d displacement slots; use fewer lanes or fused=False"
                              % (lanes, self.plan.n_atoms, N.MD_DRIFT_MAX_BLOCKS))

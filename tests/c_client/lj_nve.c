@@ -135,6 +135,7 @@ int main(int argc, char** argv) {
   nl.nneigh = (int*)dev_alloc(sizeof(int) * (size_t)n);
   nl.max_neigh = max_neigh;
   nl.lanes = lanes;
+  nl.block = 0; /* the default launch shape */
   const int cap = steps + 1;
   long long* ev = (long long*)dev_alloc(sizeof(long long) * MD_EV_LEN * (size_t)cap);
   md_lj lj = {eps, sigma, r_cut};

@@ -204,3 +204,60 @@ def test_force_matching_backward_after_another_forward(md):
     b2_alone = c2.clone().requires_grad_(True)
     fm.force_matching_loss(b2_alone, batch, pot, f_ref).backward()
     assert torch.equal(b2.grad, b2_alone.grad)
+
+
+def test_launch_shapes_and_tuner(md, tmp_path):
+    """Every launch shape the tuner may pick -- (lanes per atom, workgroup size) -- gives the
+    fixed default shape's per-replica records and forces on the 64 uneven cold-curve
+    replicas, displaced (FP64, 1e-12 relative); the tuner times each shape once, takes the
+    fastest, and reuses the cached choice for the same key without timing."""
+    from paper_2511_22951_amd import tune
+    from tests.gpu_util import rel_fro
+    reps = mi.cold_curve_replicas()
+    rng = np.random.default_rng(77)
+    for r in reps:
+        r.pos = r.pos + rng.normal(0.0, 0.05, r.pos.shape)
+    pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
+    table = pot.table(0)
+
+    def run(shape, calls=1):
+        plan, st, nl = _batch(md, reps, 0, shape[0])
+        nl.set_block(shape[1])
+        ev = md_ev(len(reps))
+        for _ in range(calls):
+            md.md_eam_forces(st, pot, nl, table=table, ev=ev)
+        st.check_flags()
+        return evv(ev)[0], st.forces(), st
+
+    e0, f0, _ = run((4, 1024))
+    # per replica: 1e-12 of the record's largest component, plus one fixed-point quantum
+    # (2^-36 eV) per tile, since a different workgroup size rounds differently grouped tile
+    # partials into the fixed-point record
+    tiles = np.array([(len(r.pos) + 63) // 64 for r in reps], np.float64)
+    tol = 1e-12 * np.max(np.abs(e0), axis=1) + tiles * 2.0 ** -36
+    assert np.max(np.abs(f0)) > 0.1
+    for shape in tune.shapes(0):
+        e, f, _ = run(shape)
+        assert np.all(np.abs(e - e0) <= tol[:, None]), shape
+        assert rel_fro(f, f0) < 1e-12, shape
+
+    calls = []
+
+    def time_fn(shape):
+        calls.append(shape)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        plan, st, nl = _batch(md, reps, 0, shape[0])
+        nl.set_block(shape[1])
+        t0.record()
+        for _ in range(3):
+            md.md_eam_forces(st, pot, nl, table=table)
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1)
+
+    path = str(tmp_path / "tune.json")
+    best = tune.pick(("cold_curve_test", "fp64"), tune.shapes(0), time_fn, cache_path=path)
+    assert best in tune.shapes(0) and sorted(calls) == sorted(tune.shapes(0))
+    n = len(calls)
+    assert tune.pick(("cold_curve_test", "fp64"), tune.shapes(0), time_fn, cache_path=path) == best
+    assert len(calls) == n
