@@ -180,14 +180,18 @@ struct FixBox {
   float inv[3];            // span / 2^32
   bool iso;                // one span on all axes
 };
+// The scale 2^32 / span comes from the domain's stored 1 / L wherever span = L (so that
+// L scale = 2^32 to 1e-16 and an image shift of L is 2^32 fixed-point units); a division
+// is left only for short non-periodic axes.
 __device__ __forceinline__ FixBox fix_box(const md_domain& D, double r_ns) {
   FixBox f;
   double span[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    span[a] = D.periodic[a] ? D.len[a] : fmax(D.len[a], 4.0 * r_ns);
+    const bool full = D.periodic[a] || D.len[a] >= 4.0 * r_ns;
+    span[a] = full ? D.len[a] : 4.0 * r_ns;
     f.lo[a] = D.lo[a];
-    f.scale[a] = 4294967296.0 / span[a];
+    f.scale[a] = full ? 4294967296.0 * D.inv_len[a] : 4294967296.0 / span[a];
     f.inv[a] = (float)(span[a] * 2.3283064365386963e-10);
   }
   f.iso = span[0] == span[1] && span[0] == span[2];

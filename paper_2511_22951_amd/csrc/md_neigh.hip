@@ -135,6 +135,31 @@ __device__ __forceinline__ int block_incl_scan(int v, int* s_w, int& total) {
   return v;
 }
 
+// The whole histogram scan in one block, for grids of at most MD_SCAN_ONE_MAX cells: each
+// thread scans a contiguous run of cells (one launch instead of three).
+#define MD_SCAN_ONE_MAX 65536
+__global__ __launch_bounds__(1024) void k_scan_one(int n_cells, int mode, int* counts,
+                                                    int* cell_start, md_ctl_dev* ctl) {
+  if (skip_rebuild(mode, ctl)) return;
+  __shared__ int s_w[17];
+  const int per = (n_cells + 1023) / 1024;
+  const int beg = min(n_cells, (int)threadIdx.x * per), end = min(n_cells, beg + per);
+  int v = 0;
+  for (int k = beg; k < end; ++k) v += counts[k];
+  int total;
+  int run = block_incl_scan(v, s_w, total) - v;
+  for (int k = beg; k < end; ++k) {
+    const int c = counts[k];
+    cell_start[k] = run;
+    run += c;
+    counts[k] = 0;
+  }
+  if (threadIdx.x == 0) {
+    cell_start[n_cells] = total;
+    ctl->n_rebuilds += 1;
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_scan_sums(int n_cells, int seg, int mode,
                                                      const int* counts, int* bsum,
                                                      md_ctl_dev* ctl) {
@@ -514,18 +539,24 @@ extern "C" int md_bin_cells(const md_batch* b, md_rebuild_mode mode, double* pos
   MD_LAUNCH_TIMED(MD_KERNEL_BIN_COUNT, k_bin_count, grid, block, 0, st, *b, (int)mode,
                   (double4*)pos, cell_of, rank_of, counts, c);
   MD_LAUNCH_CHECK();
-  const int nb = std::min(MD_SCAN_BLOCKS, (b->n_cells + 1023) / 1024);
-  const int seg = (b->n_cells + nb - 1) / nb;
-  int* bsum = (int*)(w + L.scan);
-  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(1024), 0, st, b->n_cells, seg, (int)mode,
-                     counts, bsum, c);
-  MD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, nb, b->n_cells, (int)mode, bsum,
-                     cell_start, c);
-  MD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, b->n_cells, seg, (int)mode,
-                     counts, bsum, cell_start, c);
-  MD_LAUNCH_CHECK();
+  if (b->n_cells <= MD_SCAN_ONE_MAX) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, b->n_cells, (int)mode, counts,
+                       cell_start, c);
+    MD_LAUNCH_CHECK();
+  } else {
+    const int nb = std::min(MD_SCAN_BLOCKS, (b->n_cells + 1023) / 1024);
+    const int seg = (b->n_cells + nb - 1) / nb;
+    int* bsum = (int*)(w + L.scan);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(1024), 0, st, b->n_cells, seg, (int)mode,
+                       counts, bsum, c);
+    MD_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, nb, b->n_cells, (int)mode, bsum,
+                       cell_start, c);
+    MD_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, b->n_cells, seg, (int)mode,
+                       counts, bsum, cell_start, c);
+    MD_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_bin_scatter, grid, block, 0, st, *b, (int)mode, cell_of, rank_of,
                      cell_start, id, src, sid, c);
   MD_LAUNCH_CHECK();
