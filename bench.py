@@ -110,9 +110,10 @@ def force_source_digest(read=None):
 
 
 def measured_traffic(prec_name, lanes):
-    """HBM bytes per force-pass launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE scaled by a copy calibration), or None when the summary was taken for
-    another configuration or the force-pass sources have changed since."""
+    """HBM bytes per force-pass launch of the given path ("fp32"/"fp64") from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy calibration), or None when
+    the summary was taken for another configuration or the force-pass sources have changed
+    since."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as f:
@@ -124,12 +125,10 @@ def measured_traffic(prec_name, lanes):
         digest = force_source_digest()
     except OSError:
         return None
-    if kv.get("source_sha256") != digest:
+    if kv.get("source_sha256") != digest or kv.get("lanes") != str(lanes):
         return None
-    if (kv.get("precision") != prec_name or kv.get("lanes") != str(lanes)
-            or "k_eam_force_traffic_bytes" not in kv):
-        return None
-    return float(kv["k_eam_force_traffic_bytes"])
+    key = "k_eam_force_traffic_bytes_" + prec_name
+    return float(kv[key]) if key in kv else None
 
 
 def time_kernel(md_native, kernel, run_once, samples):

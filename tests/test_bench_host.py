@@ -46,12 +46,13 @@ def test_algorithmic_bytes_of_the_force_pass():
 
 
 def test_committed_traffic_summary_matches_the_force_pass_sources():
-    # the summary under profiles/ was taken for the current sources (FP32, 2 lanes), and is
-    # not offered for another configuration
-    t = bench.measured_traffic("fp32", 2)
-    assert t is not None and 5e7 < t < 1e8
-    assert bench.measured_traffic("fp64", 2) is None
+    # the summary under profiles/ was taken for the current sources (both paths, 2 lanes),
+    # and is not offered for another configuration
+    for p in ("fp32", "fp64"):
+        t = bench.measured_traffic(p, 2)
+        assert t is not None and 5e7 < t < 1e8
     assert bench.measured_traffic("fp32", 4) is None
+    assert bench.measured_traffic("fp16", 2) is None
 
 
 def test_more_than_one_gpu_is_refused():
