@@ -96,19 +96,21 @@ __device__ __forceinline__ Sep separation(const Img& D, double4 pj, double4 pi, 
   return d;
 }
 
-// Rows of the pair tables: the r grid's intervals (FP64), the r^2 grid's (FP32).
+// Rows of the pair tables: the r grid's intervals (FP64), the r^2 grid's and its zero
+// row (FP32).
 template <typename R>
 __device__ __host__ __forceinline__ int pair_rows(const TabGeom& g) {
-  return sizeof(R) == 4 ? MD_STAB_N : g.nr;
+  return sizeof(R) == 4 ? MD_STAB_ROWS : g.nr;
 }
 
-// FP32 pair-table row and local coordinate for squared distance q (r^2 grid; the
-// index is clamped, pairs outside the table are masked or flagged by the caller).
+// FP32 pair-table row and local coordinate for squared distance q (r^2 grid).  Every q
+// at or beyond r_cut^2 lands on the zero row MD_STAB_N, so such pairs add exactly zero
+// with no compare; q below the table clamps to row 0 (flagged by the density pass).
+// t = fract(u) equals u - floor(u) exactly for u >= 0.
 __device__ __forceinline__ int qtab_index(float q, float inv_h, float lo_inv_h, float& t) {
   const float u = q * inv_h - lo_inv_h;
-  const int k = min(max((int)u, 0), MD_STAB_N - 1);
-  t = u - (float)k;
-  return k;
+  t = __builtin_amdgcn_fractf(u);
+  return min(max((int)u, 0), MD_STAB_N);
 }
 
 __device__ __forceinline__ float cubic(const float* a, float t) {
@@ -219,9 +221,9 @@ __device__ __forceinline__ void fix_sep(const uint4& q, const uint4& ri, const F
   }
 }
 
-// Fixed-point coordinates of the atoms of a batch (the x, y, z words of the FP32 EAM
-// records; the density pass adds F' in the w word).
-__global__ __launch_bounds__(MD_ATOM_BLOCK) void k_eam_records(md_batch b, const double4* pos,
+// Fixed-point coordinates of the atoms of a batch (the x, y, z words of the FP32 neighbour
+// records of the LJ and EAM passes; the EAM density pass adds F' in the w word).
+__global__ __launch_bounds__(MD_ATOM_BLOCK) void k_fix_records(md_batch b, const double4* pos,
                                                                 uint4* rec) {
   const int nlb = (b.n_tiles + 3) / 4;
   const int lane = threadIdx.x & (MD_WAVE - 1);
@@ -417,7 +419,7 @@ __device__ __forceinline__ void eam_density_body(
   double min_r2_scale = 1.0;
   if constexpr (std::is_same<R, float>::value) {
     if (i >= 0) {
-      // separations from the fixed-point records of k_eam_records (as in the force pass)
+      // separations from the fixed-point records of k_fix_records (as in the force pass)
       const FixBox X = fix_box(b.domains[T.rep], b.r_ns);
       const uint4 ri = rec[i];
       const double s = X.inv[0];
@@ -426,21 +428,18 @@ __device__ __forceinline__ void eam_density_body(
         constexpr bool ISO = decltype(iso_tag)::value;
         const float qih = (float)(ISO ? g.q_inv_h * s * s : g.q_inv_h);
         const float qloh = (float)(g.q_lo * g.q_inv_h);
-        const float rc2e = ISO ? (float)((double)rc2 / (s * s)) : rc2;
         auto pair = [&](uint4 q, bool valid) {
           float x, y, z;
           fix_sep<ISO>(q, ri, X, x, y, z);
-          // padding entries (the atom itself) are moved out of range
+          // padding entries (the atom itself) are moved beyond the cutoff
           const float r2 = valid ? x * x + y * y + z * z : 1e30f;
-          const bool in = r2 < rc2e;  // branch-free: pairs beyond r_c are masked
-          // r^2 table: no square root; below the table shows in the smallest r^2
+          // r^2 table: no square root; pairs beyond r_c read the zero row, below the
+          // table shows in the smallest r^2
           float tt;
           const float* row = rtab + qtab_index(r2, qih, qloh, tt) * MD_RTAB_W;
-          const float vr = cubic(row, tt);
-          const float vp = EV ? cubic(row + 4, tt) : 0.0f;
           min_r2 = fminf(min_r2, r2);
-          rho += in ? vr : 0.0f;
-          if (EV) phi += in ? vp : 0.0f;
+          rho += cubic(row, tt);
+          if (EV) phi += cubic(row + 4, tt);
         };
         visit_list_pipe<LANES, U>(neigh, e0, stride, S.l, nn, i,
                                   [&](int j) { return load_rec16(rec, j); }, pair);
@@ -625,16 +624,16 @@ __device__ __forceinline__ void eam_force_body(
       const float fpi = __uint_as_float(ri.w);
       const float qih = (float)g.q_inv_h, qloh = (float)(g.q_lo * g.q_inv_h);
       const E e0 = (E)i * LANES + S.l, stride = (E)npad * LANES;
-      auto pair = [&](uint4 q, bool valid) {
+      auto pair = [&](uint4 q, bool) {
         float x, y, z;
         fix_sep<false>(q, ri, X, x, y, z);
         const float r2 = x * x + y * y + z * z;
-        const bool in = valid && r2 < rc2;  // branch-free: pairs beyond r_c are masked
-        // s = [phi'(r) + (F'_i + F'_j) rho'(r)] / r; the force on i from j is s (r_j - r_i)
+        // s = [phi'(r) + (F'_i + F'_j) rho'(r)] / r; the force on i from j is s (r_j - r_i).
+        // Pairs beyond r_c read the zero row (s = 0); a padding entry is the atom itself, at
+        // zero separation, so it adds nothing either.
         float tt;
         const float* row = ftab + qtab_index(r2, qih, qloh, tt) * MD_FTAB_W;
-        const float s0 = cubic(row, tt) + (fpi + __uint_as_float(q.w)) * cubic(row + 4, tt);
-        const float sv = in ? s0 : 0.0f;
+        const float sv = cubic(row, tt) + (fpi + __uint_as_float(q.w)) * cubic(row + 4, tt);
         const float px = sv * x, py = sv * y, pz = sv * z;
         fx += px;
         fy += py;
@@ -786,7 +785,8 @@ template <typename R, int LANES, bool EV, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_lj(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, LJc c, R rc2, R* force, double* vel,
-    double inv_mass, double half_dt, DriftArgs dr, long long* ev, int ev_cap, md_ctl_dev* ctl) {
+    double inv_mass, double half_dt, DriftArgs dr, const uint4* __restrict__ rec, long long* ev,
+    int ev_cap, md_ctl_dev* ctl) {
   constexpr int U = 4;
   __shared__ double sh[MD_EV_LEN * 16];
   __shared__ double tsum[MD_EV_LEN * 16];
@@ -806,43 +806,58 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
     }
   }
   const bool wimg = __any(raw & MD_NN_IMG);
+  // the pair force, energy and virial from the separation (x, y, z) = r_j - r_i
+  auto lj_pair = [&](R x, R y, R z) {
+    const R r2 = x * x + y * y + z * z;
+    if (r2 < rc2) {
+      const R ir2 = (R)1 / r2;
+      const R sr2 = sig2 * ir2;
+      const R sr6 = sr2 * sr2 * sr2;
+      const R sr12 = sr6 * sr6;
+      // f_i = -dU/dr r_ij / r = -24 eps (2 sr12 - sr6) / r^2 (r_j - r_i)
+      const R s = -eps24 * ((R)2 * sr12 - sr6) * ir2;
+      fx += s * x;
+      fy += s * y;
+      fz += s * z;
+      if (EV) {
+        e += eps4 * (sr12 - sr6) - ucut;
+        w[0] -= s * x * x;
+        w[1] -= s * y * y;
+        w[2] -= s * z * z;
+        w[3] -= s * x * y;
+        w[4] -= s * x * z;
+        w[5] -= s * y * z;
+      }
+    }
+  };
   if (i >= 0) {
-    const Img D(&b.domains[T.rep]);
-    const double4 pi = pos[i];
     const E e0 = (E)i * LANES + S.l, stride = (E)npad * LANES;
-    auto run = [&](auto img_tag) {
-      constexpr bool IMG = decltype(img_tag)::value;
-      auto pair = [&](double4 pj) {
-        Sep sh;
-        const Sep d = separation<IMG>(D, pj, pi, sh);
-        const R x = (R)d.x, y = (R)d.y, z = (R)d.z;
-        const R r2 = x * x + y * y + z * z;
-        if (r2 < rc2) {
-          const R ir2 = (R)1 / r2;
-          const R sr2 = sig2 * ir2;
-          const R sr6 = sr2 * sr2 * sr2;
-          const R sr12 = sr6 * sr6;
-          // f_i = -dU/dr r_ij / r = -24 eps (2 sr12 - sr6) / r^2 (r_j - r_i)
-          const R s = -eps24 * ((R)2 * sr12 - sr6) * ir2;
-          fx += s * x;
-          fy += s * y;
-          fz += s * z;
-          if (EV) {
-            e += eps4 * (sr12 - sr6) - ucut;
-            w[0] -= s * x * x;
-            w[1] -= s * y * y;
-            w[2] -= s * z * z;
-            w[3] -= s * x * y;
-            w[4] -= s * x * z;
-            w[5] -= s * y * z;
-          }
-        }
+    if constexpr (std::is_same<R, float>::value) {
+      // FP32: separations from the 16-byte fixed-point records (minimum image by 32-bit
+      // wrap-around, one load per neighbour), as in the EAM passes
+      const FixBox X = fix_box(b.domains[T.rep], b.r_ns);
+      const uint4 ri = rec[i];
+      visit_list<LANES, U>(neigh, e0, stride, S.l, nn, [&](int j) { return load_rec16(rec, j); },
+                           [&](uint4 q) {
+                             float x, y, z;
+                             fix_sep<false>(q, ri, X, x, y, z);
+                             lj_pair(x, y, z);
+                           });
+    } else {
+      const Img D(&b.domains[T.rep]);
+      const double4 pi = pos[i];
+      auto run = [&](auto img_tag) {
+        constexpr bool IMG = decltype(img_tag)::value;
+        visit_list<LANES, U>(neigh, e0, stride, S.l, nn,
+                             [&](int j) { return load_rec(pos, j); }, [&](double4 pj) {
+                               Sep sh;
+                               const Sep d = separation<IMG>(D, pj, pi, sh);
+                               lj_pair(d.x, d.y, d.z);
+                             });
       };
-      visit_list<LANES, U>(neigh, e0, stride, S.l, nn, [&](int j) { return load_rec(pos, j); },
-                           pair);
-    };
-    if (wimg) run(std::true_type{});
-    else run(std::false_type{});
+      if (wimg) run(std::true_type{});
+      else run(std::false_type{});
+    }
   }
   fx = md_group_sum<LANES>(fx);
   fy = md_group_sum<LANES>(fy);
@@ -977,7 +992,7 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
   const bool big = md_big_list(nl, npad);
   int st_ = MD_OK;
   if (rec)
-    hipLaunchKernelGGL(k_eam_records, dim3(md_atom_grid(b.n_tiles)), dim3(MD_ATOM_BLOCK), 0, st, b,
+    hipLaunchKernelGGL(k_fix_records, dim3(md_atom_grid(b.n_tiles)), dim3(MD_ATOM_BLOCK), 0, st, b,
                        (const double4*)pos, rec);
 #define MD_EAM_LAUNCH_E(EVB, TL_)                      \
   do {                                                 \
@@ -999,7 +1014,8 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
 template <typename R, int LANES>
 void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nlist& nl,
                void* force, double* vel, double inv_mass, double half_dt, const DriftArgs& dr,
-               long long* ev, int ev_cap, md_ctl_dev* ctl, hipStream_t st) {
+               long long* ev, int ev_cap, uint4* rec_ws, md_ctl_dev* ctl, hipStream_t st) {
+  uint4* rec = std::is_same<R, float>::value ? rec_ws : nullptr;  // FP32: fixed-point records
   LJc c;
   c.sig2 = p.sigma * p.sigma;
   c.eps4 = 4.0 * p.eps;
@@ -1014,7 +1030,10 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
 #define MD_LJ_LAUNCH(EVB, E_)                                                                  \
   MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, EVB, E_>), grid, block, 0, st, b,             \
                   (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,      \
-                  inv_mass, half_dt, dr, ev, ev_cap, ctl)
+                  inv_mass, half_dt, dr, rec, ev, ev_cap, ctl)
+  if (rec)
+    hipLaunchKernelGGL(k_fix_records, dim3(md_atom_grid(b.n_tiles)), dim3(MD_ATOM_BLOCK), 0, st, b,
+                       (const double4*)pos, rec);
   hipLaunchKernelGGL(k_lj_prologue, dim3(1), dim3(1024), 0, st, b, ev, ev_cap, ctl);
   if (ev) {
     if (big) MD_LJ_LAUNCH(true, uint64_t);
@@ -1174,14 +1193,15 @@ extern "C" int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec
   if (b->n_atoms == 0 || b->n_tiles == 0) return MD_OK;
   hipStream_t st = (hipStream_t)stream;
   md_ctl_dev* c = (md_ctl_dev*)ctl;
+  uint4* rec = (uint4*)((char*)ws + md_ws_plan(b).rec);
   if (prec == MD_FP32) {
     MD_DISPATCH_LANES(nl->lanes, (launch_lj<float, L_>(*b, *p, pos, *nl, force, vel, inv_mass,
-                                                       half_dt, dr, (long long*)ev, ev_cap, c,
-                                                       st)));
+                                                       half_dt, dr, (long long*)ev, ev_cap, rec,
+                                                       c, st)));
   } else {
     MD_DISPATCH_LANES(nl->lanes, (launch_lj<double, L_>(*b, *p, pos, *nl, force, vel, inv_mass,
-                                                        half_dt, dr, (long long*)ev, ev_cap, c,
-                                                        st)));
+                                                        half_dt, dr, (long long*)ev, ev_cap, rec,
+                                                        c, st)));
   }
   MD_LAUNCH_CHECK();
   return MD_OK;

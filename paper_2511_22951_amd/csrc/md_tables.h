@@ -14,6 +14,8 @@
 // FP64; interpolation error ~1e-10 relative for the 2000-point tables):
 //   rtab[k][8] = {rho a0..a3, phi a0..a3}
 //   ftab[k][8] = {phi'/r a0..a3, rho'/r a0..a3}            (G(q) = s'(r) / r)
+// followed by one row of zeros (k = MD_STAB_N): the pair loops clamp every q beyond
+// r_cut^2 onto it, so that pairs past the cutoff add exactly zero without a compare.
 // The embedding table stays on the rhobar grid as above.
 #pragma once
 
@@ -23,6 +25,7 @@
 #define MD_FTAB_W 8
 #define MD_ETAB_W 16
 #define MD_STAB_N 2000  // FP32 pair tables: intervals in r^2 (2000 x 32 B fits 64 KB of LDS)
+#define MD_STAB_ROWS (MD_STAB_N + 1)  // FP32 pair-table rows: the intervals and the zero row
 
 struct md_table_layout {
   size_t rtab, ftab, etab, total;

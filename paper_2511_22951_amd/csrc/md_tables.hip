@@ -102,7 +102,12 @@ __device__ void hermite(double f0, double g0, double f1, double g1, float* a) {
 // d/dq s(r) = s'(r) / (2 r), and for G = s'(r) / r, dG/dq = (r s'' - s') / (2 r^3).
 __global__ void k_eam_prepare_q(md_eam p, double q_lo, double h_q, float* rtab, float* ftab) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= MD_STAB_N) return;
+  if (k >= MD_STAB_ROWS) return;
+  if (k == MD_STAB_N) {  // beyond r_cut: zero
+    for (int m = 0; m < MD_RTAB_W; ++m) rtab[(size_t)k * MD_RTAB_W + m] = 0.0f;
+    for (int m = 0; m < MD_FTAB_W; ++m) ftab[(size_t)k * MD_FTAB_W + m] = 0.0f;
+    return;
+  }
   const int nr = p.rho.ncoef - 3;
   double val[2][2], dq[2][2], G[2][2], dG[2][2];  // [end][phi, rho]
   for (int e = 0; e < 2; ++e) {
@@ -138,7 +143,7 @@ md_table_layout md_table_plan(const md_eam* p, md_precision prec) {
   md_table_layout L;
   const size_t es = prec == MD_FP32 ? 4 : 8;
   const size_t ne = (size_t)(p->emb.ncoef - 3);
-  const size_t nr = prec == MD_FP32 ? (size_t)MD_STAB_N : (size_t)(p->rho.ncoef - 3);
+  const size_t nr = prec == MD_FP32 ? (size_t)MD_STAB_ROWS : (size_t)(p->rho.ncoef - 3);
   L.rtab = 0;
   L.ftab = md_align256(nr * MD_RTAB_W * es);
   L.etab = L.ftab + md_align256(nr * MD_FTAB_W * es);
@@ -186,7 +191,7 @@ extern "C" int md_eam_prepare(const md_eam* p, md_precision prec, void* table, v
                        (float*)nullptr, (float*)nullptr, (float*)(t + L.etab));
     MD_LAUNCH_CHECK();
     const md_qgrid q = md_qgrid_plan(p);
-    hipLaunchKernelGGL(k_eam_prepare_q, dim3((MD_STAB_N + 255) / 256), dim3(256), 0,
+    hipLaunchKernelGGL(k_eam_prepare_q, dim3((MD_STAB_ROWS + 255) / 256), dim3(256), 0,
                        (hipStream_t)stream, *p, q.q_lo, q.h, (float*)(t + L.rtab),
                        (float*)(t + L.ftab));
   } else
