@@ -293,6 +293,38 @@ def autotune_lanes(system, prec):
     return tune.best_lanes(system, prec)
 
 
+def cpu_baseline_one_core(n_full, cells=16):
+    """The same FP64 O(N^2) oracle step on one host thread, on a bounded sample: the Cu workload
+    at cells^3 fcc cells (16,384 atoms by default), timed whole.  Its pair work per atom is
+    m / n_full of the full box's, so the rate per atom-step scales to the full box by m / n_full;
+    both figures are reported."""
+    import mdinputs as mi
+    from oracle import core, integrate
+    core.lib()  # loads the oracle and the OpenMP runtime it links
+    gomp = C.CDLL("libgomp.so.1")
+    prev = core.num_threads()
+    small = mi.eam_copper(cells=cells)
+    pot = core.EAMPotential.from_table(small.table)
+    gomp.omp_set_num_threads(1)
+    try:
+        threads = core.num_threads()
+        x = core.wrap(small.pos, small.box)
+        t0 = time.perf_counter()
+        r = core.eam(x, small.box, pot)
+        v = small.vel + 0.5 * small.dt_ps * r.force / small.mass * integrate.ACCEL
+        x = x + small.dt_ps * v
+        dt = time.perf_counter() - t0
+    finally:
+        gomp.omp_set_num_threads(prev)
+    m = x.shape[0]
+    return {"value": m / dt * m / n_full, "unit": "atom-steps/s", "cores": threads,
+            "kind": "oracle", "rate_at_sample": m / dt,
+            "sample": "one full FP64 O(N^2) step (density + force + Verlet) of the same Cu "
+                      "workload at %d^3 cells (%d atoms) on one thread, %.1f s; the O(N^2) "
+                      "work per atom scales the rate to %d atoms by %d/%d"
+                      % (cells, m, dt, n_full, m, n_full)}
+
+
 def cpu_baseline(system, f_gpu):
     """FP64 O(N^2) oracle: one full step (density pass, force pass, velocity Verlet) of the
     same initial state, on all host threads.  Also returns the GPU step-0 force errors."""
@@ -400,9 +432,10 @@ def main():
 
     f_gpu = {k: r["f0"] for k, r in results.items()}
     if args.no_cpu_baseline:
-        cpu, ferr, e_or = None, {}, None
+        cpu, ferr, e_or, cpu1 = None, {}, None, None
     else:
         cpu, ferr, e_or = cpu_baseline(system, f_gpu)
+        cpu1 = cpu_baseline_one_core(n)
 
     out = {
         "metric": "atom-steps/s (EAM Cu force+Verlet) FP32 vs FP64 at stated force error",
@@ -423,6 +456,7 @@ def main():
                    "timed_region": R["timed"]},
         "roofline": dict(roofline(head), copy_ceiling_GBs=copy_ceiling_gbs()),
         "cpu_baseline": cpu,
+        "cpu_baseline_one_core": cpu1,
     }
     if head != "fp64" and "fp64" in results:
         out["roofline_fp64"] = roofline("fp64")

@@ -9,6 +9,9 @@
   lone atom                no neighbours: LJ force and energy exactly zero; EAM density 0
                            lies below the embedding table, so MD_ERR_TABLE_RANGE is reported
                            (the oracle flags the same atom)
+  pairs past the cutoff    listed pairs with r_c < r < r_ns (the FP32 tables' zero row, the
+                           FP64 mask) add exactly nothing: an EAM dimer's forces are bit for
+                           bit those with the second dimer far away
   dimer                    LJ force and energy equal the closed form of eq. 1.6 (FP64 to
                            1e-14, FP32 to 1e-6); virial equal to the oracle's.  EAM: energy
                            2 F(rho(r)) + phi(r) and the pair force with both atoms' F' from the
@@ -207,3 +210,26 @@ def test_eam_dimer_closed_form(prec, tol_e):
     assert abs(rec[0, 0] - e) <= tol_e * abs(e)
     assert np.max(np.abs(f[1] + dedr * unit)) <= 5e-6 * abs(dedr)
     assert np.max(np.abs(f[0] - dedr * unit)) <= 5e-6 * abs(dedr)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_eam_listed_pairs_past_the_cutoff_add_nothing(prec):
+    """Two Cu dimers (2.5 A bonds) whose atoms face each other at 5.6 A, between r_c = 5.5 and
+    r_ns = 5.8: the cross pairs are listed but lie past the cutoff, so the first dimer's forces
+    equal, bit for bit, those with the second dimer moved far away, and the energy is twice
+    the lone dimer's."""
+    from paper_2511_22951_amd import md
+    box = mi.Box((0.0, 0.0, 0.0), (40.0, 40.0, 40.0), (1, 1, 1))
+    a, b = np.array([10.0, 10.0, 10.0]), np.array([12.5, 10.0, 10.0])
+    near = np.array([a, b, a + [0.0, 0.0, 5.6], b + [0.0, 0.0, 5.6]])
+    far = np.array([a, b, a + [0.0, 0.0, 15.6], b + [0.0, 0.0, 15.6]])
+    got = {}
+    for name, x in (("near", near), ("far", far)):
+        st, nl, rec = _run(md, [(x, box)], "eam", prec)
+        ids = st.id.cpu().numpy()
+        nn = nl.lengths().cpu().numpy()
+        f = st.forces()  # by original id
+        got[name] = (f, rec[0, 0], {int(ids[k]): int(nn[k]) for k in range(len(ids))})
+    assert got["near"][2][0] == 2 and got["far"][2][0] == 1  # the cross pair is listed
+    assert np.array_equal(got["near"][0][:2], got["far"][0][:2])
+    assert abs(got["near"][1] - got["far"][1]) <= 1e-9
