@@ -83,6 +83,11 @@ def algorithmic_force_bytes(n_atoms, mean_neigh, force_bytes, fused=False):
 FORCE_SOURCES = ("paper_2511_22951_amd/csrc/md_force.hip", "paper_2511_22951_amd/csrc/md_internal.h",
                  "paper_2511_22951_amd/csrc/md_tables.h", "include/md.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eam_cu131k_hbm_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "eam_cu131k_counters.txt")
+# VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 clocks
+# at 2.4 GHz (the 78.6 TFLOP/s vector peak counted per instruction: an FMA is 2 flops on
+# each of 64 lanes)
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def strip_c_comments(text):
@@ -109,14 +114,13 @@ def force_source_digest(read=None):
     return h.hexdigest()
 
 
-def measured_traffic(prec_name, lanes):
-    """HBM bytes per force-pass launch of the given path ("fp32"/"fp64") from the committed
-    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy calibration), or None when
-    the summary was taken for another configuration or the force-pass sources have changed
-    since."""
+def _summary_values(path, lanes):
+    """The `key = value` lines of a committed counter summary, or None when the summary was
+    taken for another lanes-per-atom configuration or the force-pass sources have changed
+    since (its source_sha256 differs from force_source_digest())."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             text = f.read()
         for line in text.splitlines():
             if " = " in line:
@@ -127,8 +131,26 @@ def measured_traffic(prec_name, lanes):
         return None
     if kv.get("source_sha256") != digest or kv.get("lanes") != str(lanes):
         return None
+    return kv
+
+
+def measured_traffic(prec_name, lanes):
+    """HBM bytes per force-pass launch of the given path ("fp32"/"fp64") from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy calibration), or None when
+    the summary was taken for another configuration or the force-pass sources have changed
+    since."""
+    kv = _summary_values(TRAFFIC_FILE, lanes)
     key = "k_eam_force_traffic_bytes_" + prec_name
-    return float(kv[key]) if key in kv else None
+    return float(kv[key]) if kv and key in kv else None
+
+
+def measured_valu(prec_name, lanes):
+    """VALU wave-instructions per force-pass launch (SQ_INSTS_VALU over the launch's waves)
+    from the committed pipeline-counter summary, under the same conditions as
+    measured_traffic."""
+    kv = _summary_values(COUNTERS_FILE, lanes)
+    key = "valu_wave_instructions_k_eam_force_" + ("f32" if prec_name == "fp32" else "f64")
+    return float(kv[key]) if kv and key in kv else None
 
 
 def time_kernel(md_native, kernel, run_once, samples):
@@ -425,10 +447,14 @@ def main():
         nbytes = algorithmic_force_bytes(n, r["mean_neigh"], 4 if name == "fp32" else 8,
                                          fused=not args.unfused)
         a = nbytes / kt / 1e9
+        vi = measured_valu(name, r["lanes"])
+        valu = None if vi is None else {
+            "achieved": vi / kt, "peak": VALU_ISSUE_PEAK, "unit": "wave-instructions/s",
+            "frac": vi / kt / VALU_ISSUE_PEAK, "instructions_per_launch": vi}
         return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": a / HBM_PEAK_GBS, "traffic": measured_traffic(name, r["lanes"]),
                 "kernel": "k_eam_force_" + ("f32" if name == "fp32" else "f64"),
-                "kernel_us": kt * 1e6, "bytes_per_launch": nbytes}
+                "kernel_us": kt * 1e6, "bytes_per_launch": nbytes, "valu": valu}
 
     f_gpu = {k: r["f0"] for k, r in results.items()}
     if args.no_cpu_baseline:

@@ -55,6 +55,16 @@ def test_committed_traffic_summary_matches_the_force_pass_sources():
     assert bench.measured_traffic("fp16", 2) is None
 
 
+def test_committed_valu_counts_match_the_force_pass_sources():
+    # the VALU instruction counts beside the HBM roofline come from the counter summary of the
+    # current sources: per launch 4096 waves of 1.5k-3k instructions each
+    for p in ("fp32", "fp64"):
+        v = bench.measured_valu(p, 2)
+        assert v is not None and 4096 * 1500 < v < 4096 * 3000
+    assert bench.measured_valu("fp32", 4) is None
+    assert 6.1e11 < bench.VALU_ISSUE_PEAK < 6.2e11
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
