@@ -367,6 +367,18 @@ def cpu_baseline(system, f_gpu):
                       "%.1f s" % (n, dt)}, errs, float(r.energy / n)
 
 
+def device_info():
+    """The device's unit counts and memories as the runtime reports them (to confirm the
+    figures the rooflines use: 256 CUs, wave64, 4 MB L2 per XCD, 160 KB LDS per CU)."""
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None),
+            "compute_units": p.multi_processor_count, "wavefront": p.warp_size,
+            "l2_bytes": getattr(p, "L2_cache_size", None),
+            "lds_bytes_per_block": getattr(p, "shared_memory_per_block", None),
+            "hbm_bytes": p.total_memory}
+
+
 def copy_ceiling_gbs(mib=1024, reps=5):
     """Measured device-to-device copy rate (bytes read + written per second), the
     achievable streaming ceiling beside the 8 TB/s peak (outside any timed region)."""
@@ -481,6 +493,7 @@ def main():
                    "n_atoms": n, "precision": head, "lanes_per_atom": R["lanes"],
                    "timed_region": R["timed"]},
         "roofline": dict(roofline(head), copy_ceiling_GBs=copy_ceiling_gbs()),
+        "device": device_info(),
         "cpu_baseline": cpu,
         "cpu_baseline_one_core": cpu1,
     }
