@@ -50,3 +50,27 @@ def test_noalloc_equals_workspace_entry_point(md, prec, lanes):
         for a, b in zip(*out):
             assert torch.equal(a, b)
         assert torch.count_nonzero(out[0][0]) > 0 and torch.count_nonzero(out[0][5]) > 0
+
+
+def test_noalloc_at_its_maximum_size(md):
+    """At exactly MD_NOALLOC_MAX_ATOMS atoms (Cu fcc 64^3 = 2^20, 16,384 tiles) the static
+    scratch is filled to its end: FP32 (whose neighbour records use the whole record region),
+    bit for bit against md_eam_forces, then a small system on the same scratch."""
+    from paper_2511_22951_amd import _native as N
+    for cells in (64, 5):
+        system = mi.eam_copper(cells=cells)
+        if cells == 64:
+            assert len(system.pos) == N.MD_NOALLOC_MAX_ATOMS
+        pot = md.EAMPotential.from_table(system.table)
+        out = []
+        for fn in (md.md_eam_forces, md.md_eam_forces_noalloc):
+            st, nl = _state(md, system, 1, 2)
+            ev = md.ev_buffer(4, 1, "cuda")
+            fn(st, pot, nl, inv_mass=1.0 / system.mass, half_dt=0.5 * system.dt_ps, kick=True,
+               ev=ev, ev_cap=4)
+            st.check_flags()
+            torch.cuda.synchronize()
+            out.append([st.force.clone(), st.vel.clone(), ev.clone()])
+        for a, b in zip(*out):
+            assert torch.equal(a, b)
+        assert torch.count_nonzero(out[0][0]) > 0
