@@ -6,6 +6,7 @@ size.
   neighbour sets of sampled atoms (after a rebuild at the evolved positions)   bit-exact
   forces of sampled atoms, FP64 / FP32-mixed (norm over the sample)           1e-11 / 1e-5
   net force over all atoms, relative to the sum of |F_i|, FP64 / FP32          1e-10 / 1e-5
+  force-matching adjoint (1024 snapshots), cotangent on 16 sampled snapshots   1e-10
 """
 import numpy as np
 import pytest
@@ -114,3 +115,25 @@ def test_lj13m_paper_configuration():
         if prec == N.MD_FP64:
             _check_sets(sim, s, sample)
         del sim
+
+
+def test_force_matching_1024_snapshots_vjp_sampled():
+    """The force-matching batch at its size (1024 Cu snapshots x 500 atoms, 192 spline
+    coefficients, FP64, 4 lanes per atom as bench.py runs it): the adjoint of a cotangent that
+    is nonzero on 16 sampled snapshots only equals the oracle's chain-rule VJP over those
+    snapshots alone (the VJP is linear in the cotangent and snapshots do not interact), to
+    1e-10 of its largest entry."""
+    from paper_2511_22951_amd import md
+    from oracle import adjoint as oadj
+    from tests.test_gpu_batch_adjoint import _fm_problem
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, n_snap=1024)
+    assert sum(len(s.pos) for s in snaps) == 512000
+    pick = np.sort(np.random.default_rng(2027).choice(len(snaps), 16, replace=False))
+    G = [np.zeros((len(s.pos), 3)) for s in snaps]
+    for k in pick:
+        G[k] = mi.random_cotangent(len(snaps[k].pos), seed=100 + int(k))
+    want = np.concatenate(oadj.vjp([osnaps[k] for k in pick], c_or, grids, [G[k] for k in pick]))
+    batch.forces(pot, saved=True)
+    got = batch.backward(pot, batch.to_current_order(np.concatenate(G))).cpu().numpy()
+    batch.state.check_flags()
+    assert np.max(np.abs(got - want)) < 1e-10 * np.max(np.abs(want))
