@@ -54,8 +54,11 @@ typedef enum {
   MD_ERR_NONFINITE = -6,      /* a position became NaN or infinite */
   MD_ERR_HIP = -7,            /* a HIP runtime call failed */
   MD_ERR_WORKSPACE = -8,      /* workspace or capacity too small */
-  MD_ERR_STALE_LIST = -9      /* an atom moved more than half the skin since the last list
+  MD_ERR_STALE_LIST = -9,     /* an atom moved more than half the skin since the last list
                                  build and no rebuild followed (forces may miss pairs) */
+  MD_ERR_STALE_RECORDS = -10  /* a force call was told its carried FP32 neighbour records
+                                 were current (md_drift.rec_current) after positions had
+                                 changed otherwise */
 } md_status;
 
 /* Device flag bits (md_read_flags output). */
@@ -64,6 +67,7 @@ typedef enum {
 #define MD_FLAG_WALL 4
 #define MD_FLAG_NONFINITE 8
 #define MD_FLAG_STALE_LIST 16
+#define MD_FLAG_STALE_RECORDS 32
 
 typedef enum { MD_FP64 = 0, MD_FP32 = 1 } md_precision; /* MD_FP32: FP32 pair math and
                                                           force accumulation, FP64
@@ -297,7 +301,24 @@ int md_build_neighbors(const md_batch* b, md_rebuild_mode mode, const double* po
  * the half step n + 1/2; the record of step n holds the kinetic energy at v(n).
  * The force pass keeps one displacement slot per block: MD_ERR_ARG when its grid of
  * ceil(n_tiles * lanes / 16) blocks (rounded up to a multiple of 8) exceeds
- * MD_DRIFT_MAX_BLOCKS. */
+ * MD_DRIFT_MAX_BLOCKS.
+ *
+ * FP32 neighbour records carried from step to step (MD_FP32 only; both NULL otherwise
+ * ignored).  The FP32 passes gather 16-byte records per atom (32-bit fixed-point x, y, z
+ * and F'), which a call normally makes from pos in its workspace.  rec_out (device,
+ * 16-byte aligned, 16 n bytes): the fused kick-drift also writes the records of pos_out
+ * there.  rec_in: the records of pos, as an earlier call wrote them to its rec_out; the
+ * call then uses that buffer instead of its workspace's (writing F' into it) and remakes
+ * the records from pos only when positions changed since by anything else the library
+ * does -- md_ctl_init, md_bin_cells reordering the atoms, md_verlet_step's drift -- which
+ * the control block records on the device.  The caller owns this contract: positions
+ * written outside the library since that earlier call void rec_in (pass NULL, or call
+ * md_ctl_init).  rec_in and rec_out must be different buffers (MD_ERR_ARG).
+ * rec_current = 1 declares more: that nothing changed positions since the call that wrote
+ * rec_in (no md_bin_cells, md_verlet_step or md_ctl_init in between), so the call does not
+ * even launch the check; should the control block say otherwise, the records are still
+ * used as they are and MD_FLAG_STALE_RECORDS is raised (md_read_flags then returns
+ * MD_ERR_STALE_RECORDS and the step is void). */
 #define MD_DRIFT_MAX_BLOCKS 32768
 typedef struct md_drift {
   double* pos_out;
@@ -305,6 +326,10 @@ typedef struct md_drift {
   double dt;
   double half_skin;      /* < 0: no criterion */
   md_walls walls;        /* walls.enabled = 0: none */
+  void* rec_in;          /* FP32 neighbour records of pos, or NULL */
+  void* rec_out;         /* FP32 neighbour records of pos_out are written here, or NULL */
+  int rec_current;       /* 1: rec_in is known to be current (see above); 0: checked */
+  int pad;
 } md_drift;
 
 /* Lennard-Jones forces (eq. 1.6), energy and virial.  force is [3][n] FP64 or

@@ -16,9 +16,11 @@ MD_EV_SCALE = 2.0 ** 36  # fixed-point units per eV of the per-box records
 MD_TILE = 64
 MD_NN_IMG = 1 << 30
 FLAG_NEIGH_OVERFLOW, FLAG_TABLE_RANGE, FLAG_WALL, FLAG_NONFINITE, FLAG_STALE_LIST = 1, 2, 4, 8, 16
+FLAG_STALE_RECORDS = 32
 MD_ERR_ARG = -1
 MD_DRIFT_MAX_BLOCKS = 32768
 MD_ERR_STALE_LIST = -9
+MD_ERR_STALE_RECORDS = -10
 MD_ERR_WORKSPACE = -8
 MD_NOALLOC_MAX_ATOMS = 1 << 20
 MD_NOALLOC_MAX_TILES = 32768
@@ -103,7 +105,8 @@ class BPNN(C.Structure):
 
 class Drift(C.Structure):
     _fields_ = [("pos_out", C.c_void_p), ("pos_ref", C.c_void_p), ("dt", C.c_double),
-                ("half_skin", C.c_double), ("walls", Walls)]
+                ("half_skin", C.c_double), ("walls", Walls), ("rec_in", C.c_void_p),
+                ("rec_out", C.c_void_p), ("rec_current", C.c_int), ("pad", C.c_int)]
 
 
 _lib = None

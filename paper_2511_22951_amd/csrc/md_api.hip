@@ -130,7 +130,7 @@ __global__ void k_ctl_init(md_ctl_dev* ctl) {
     ctl->max_nneigh = 0;
     ctl->n_dmax = 0;
     ctl->step_next = 0;
-    ctl->pad = 0;
+    ctl->rec_stale = 1;
     ctl->thr2 = -1.0;
     ctl->pad2 = 0.0;
   }
@@ -174,6 +174,7 @@ extern "C" int md_read_flags(const void* ctl, int* host_out, void* stream) {
   host_out[3] = h.max_nneigh;
   if (h.flags & MD_FLAG_NONFINITE) return MD_ERR_NONFINITE;
   if (h.flags & MD_FLAG_STALE_LIST) return MD_ERR_STALE_LIST;
+  if (h.flags & MD_FLAG_STALE_RECORDS) return MD_ERR_STALE_RECORDS;
   if (h.flags & MD_FLAG_NEIGH_OVERFLOW) return MD_ERR_NEIGH_OVERFLOW;
   if (h.flags & MD_FLAG_WALL) return MD_ERR_WALL;
   if (h.flags & MD_FLAG_TABLE_RANGE) return MD_ERR_TABLE_RANGE;
@@ -192,6 +193,7 @@ extern "C" const char* md_status_string(int s) {
     case MD_ERR_HIP: return "HIP runtime error";
     case MD_ERR_WORKSPACE: return "workspace or capacity too small";
     case MD_ERR_STALE_LIST: return "an atom moved more than half the skin without a list rebuild";
+    case MD_ERR_STALE_RECORDS: return "carried FP32 neighbour records declared current after positions changed";
     default: return "unknown status";
   }
 }

@@ -223,8 +223,12 @@ __device__ __forceinline__ void fix_sep(const uint4& q, const uint4& ri, const F
 
 // Fixed-point coordinates of the atoms of a batch (the x, y, z words of the FP32 neighbour
 // records of the LJ and EAM passes; the EAM density pass adds F' in the w word).
+// ctl: not NULL when the records were carried over from the last force pass (md_drift.rec_in):
+// they are then remade only if positions changed since by anything else (ctl->rec_stale).
 __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_fix_records(md_batch b, const double4* pos,
-                                                                uint4* rec) {
+                                                                uint4* rec,
+                                                                const md_ctl_dev* ctl) {
+  if (ctl && !ctl->rec_stale) return;
   const int nlb = (b.n_tiles + 3) / 4;
   const int lane = threadIdx.x & (MD_WAVE - 1);
   for (int k = 0;; ++k) {
@@ -384,7 +388,6 @@ __device__ __forceinline__ double write_force_kick(int i, int n, R fx, R fy, R f
   return 0.5 / (inv_mass * MD_ACCEL) * (vx * vx + vy * vy + vz * vz);
 }
 
-__device__ __forceinline__ void step_bookkeeping(md_ctl_dev* ctl) { md_step_bookkeeping(ctl); }
 
 // ---------------------------------------------------------------------------
 // EAM pass 1: rhobar_i = sum_j rho(r_ij), F'(rhobar_i) into pos[i].w, energy.
@@ -394,12 +397,12 @@ __device__ __forceinline__ void eam_density_body(
     const md_batch& b, double4* pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const R* __restrict__ rtab_g,
     const R* __restrict__ etab, const TabGeom& g, R rc2, double* saved, double* partial,
-    uint4* rec, long long* ev, int ev_cap, md_ctl_dev* ctl) {
+    uint4* rec, long long* ev, int ev_cap, int rec_verify, md_ctl_dev* ctl) {
   extern __shared__ float4 s_dyn[];
   __shared__ double sh[MD_EV_LEN * 16];
   const R* rtab = TLDS ? stage_table<R, MD_RTAB_W>(rtab_g, pair_rows<R>(g), (R*)s_dyn) : rtab_g;
   if (EV && blockIdx.x == 0) zero_record(b, ev, ev_cap, ctl->step_next);
-  step_bookkeeping(ctl);
+  md_step_bookkeeping(ctl, rec_verify != 0);
   const Slot S = force_slot<LANES>(b.n_tiles);
   double e_acc = 0.0;
   bool oor = false;
@@ -527,16 +530,17 @@ __device__ __forceinline__ void eam_density_body(
 #define MD_EAM_DENSITY_ARGS(R)                                                                 \
   md_batch b, double4 *pos, const int *__restrict__ neigh, const int *__restrict__ nneigh,   \
       int npad, const R *__restrict__ rtab_g, const R *__restrict__ etab, TabGeom g, R rc2,  \
-      double *saved, double *partial, uint4 *rec, long long *ev, int ev_cap, md_ctl_dev *ctl
+      double *saved, double *partial, uint4 *rec, long long *ev, int ev_cap, int rec_verify,    \
+      md_ctl_dev *ctl
 template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_density_f32(MD_EAM_DENSITY_ARGS(float)) {
   eam_density_body<float, LANES, EV, TLDS, 8, E>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
-                                           saved, partial, rec, ev, ev_cap, ctl);
+                                           saved, partial, rec, ev, ev_cap, rec_verify, ctl);
 }
 template <int LANES, bool EV, bool TLDS, typename E>
 __global__ __launch_bounds__(FBLOCK) void k_eam_density_f64(MD_EAM_DENSITY_ARGS(double)) {
   eam_density_body<double, LANES, EV, TLDS, 4, E>(b, pos, neigh, nneigh, npad, rtab_g, etab, g, rc2,
-                                            saved, partial, nullptr, ev, ev_cap, ctl);
+                                            saved, partial, nullptr, ev, ev_cap, rec_verify, ctl);
 }
 #undef MD_EAM_DENSITY_ARGS
 
@@ -552,18 +556,23 @@ struct DriftArgs {
   const double* pos_ref;
   double dt, thr2;
   md_walls_dev w;
+  uint4* rec_in;   // FP32 records of pos carried over from the last force pass, or nullptr
+  uint4* rec_out;  // FP32 records of pos_out written by the fused drift, or nullptr
+  int rec_current; // rec_in declared current: no records kernel, verified on the device
 };
 
 // Epilogue of a force pass with the next kick-drift fused in: write the force, apply
 // the trailing half kick of this step (its kinetic energy is returned), then the next
 // step's half kick and drift with the walls at (step + 1) dt -- the same operations, in
 // the same order, as md_verlet_step(MD_KICK_DRIFT) -- into dr.pos_out; d2max gets the
-// atom's displacement from x_ref.
+// atom's displacement from x_ref.  In FP32 with dr.rec_out, the new position's fixed-point
+// record (as k_fix_records would make it, in the atom's box D) goes there too.
 template <typename R>
 __device__ __forceinline__ double fused_kick_drift(int i, int n, R fx, R fy, R fz, R* force,
                                                    double* vel, double inv_mass, double half_dt,
                                                    const double4* pos, const DriftArgs& dr,
-                                                   int step, double& d2max, int& bad) {
+                                                   int step, const md_domain& D, double r_ns,
+                                                   double& d2max, int& bad) {
   force[i] = fx;
   force[n + i] = fy;
   force[2 * n + i] = fz;
@@ -581,6 +590,12 @@ __device__ __forceinline__ double fused_kick_drift(int i, int n, R fx, R fy, R f
   vel[n + i] = v[1];
   vel[2 * n + i] = v[2];
   dr.pos_out[i] = make_double4(x[0], x[1], x[2], p.w);
+  if (std::is_same<R, float>::value && dr.rec_out) {
+    const FixBox X = fix_box(D, r_ns);
+    dr.rec_out[i] = make_uint4(fix_coord(x[0], X.lo[0], X.scale[0]),
+                               fix_coord(x[1], X.lo[1], X.scale[1]),
+                               fix_coord(x[2], X.lo[2], X.scale[2]), 0u);
+  }
   if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) bad |= MD_FLAG_NONFINITE;
   d2max = md_disp2(x, dr.pos_ref, i, n);
   return ke;
@@ -709,7 +724,7 @@ __device__ __forceinline__ void eam_force_body(
   if (i >= 0 && S.l == 0) {
     if (dr.pos_out) {
       acc[6] = fused_kick_drift<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt, pos,
-                                   dr, ctl->step, d2max, bad);
+                                   dr, ctl->step, b.domains[T.rep], b.r_ns, d2max, bad);
     } else {
       acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
     }
@@ -769,8 +784,8 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_force_f64(MD_EAM_FORCE_ARGS(doub
 // a kernel of its own keeps the step counter and the displacement maxima fixed while
 // the LJ pass runs (its fused kick-drift publishes new maxima).
 __global__ __launch_bounds__(1024) void k_lj_prologue(md_batch b, long long* ev, int ev_cap,
-                                                     md_ctl_dev* ctl) {
-  md_step_bookkeeping(ctl);
+                                                     int rec_verify, md_ctl_dev* ctl) {
+  md_step_bookkeeping(ctl, rec_verify != 0);
   if (ev) zero_record(b, ev, ev_cap, ctl->step_next);
 }
 
@@ -867,7 +882,7 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
   if (i >= 0 && S.l == 0) {
     if (dr.pos_out)
       acc[7] = fused_kick_drift<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt, pos,
-                                   dr, ctl->step, d2max, bad);
+                                   dr, ctl->step, b.domains[T.rep], b.r_ns, d2max, bad);
     else
       acc[7] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
   }
@@ -936,7 +951,8 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
                 const double* pos, const md_nlist& nl, void* force, double* saved, double* vel,
                 double inv_mass, double half_dt, const DriftArgs& dr, long long* ev, int ev_cap,
                 double* partial, uint4* rec_ws, md_ctl_dev* ctl, hipStream_t st) {
-  uint4* rec = std::is_same<R, float>::value ? rec_ws : nullptr;  // FP32: fixed-point records
+  // FP32: fixed-point records, carried over (md_drift.rec_in) or in the workspace
+  uint4* rec = std::is_same<R, float>::value ? (dr.rec_in ? dr.rec_in : rec_ws) : nullptr;
   TabGeom g;
   g.r_lo = p.rho.x_lo;
   g.r_inv_h = 1.0 / p.rho.h;
@@ -965,13 +981,13 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
         return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f32<LANES, EVB, TL_, E_>), grid, block, \
                       lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
-                      rc2, saved, partial, rec, ev, ev_cap, ctl);                              \
+                      rc2, saved, partial, rec, ev, ev_cap, dr.rec_current, ctl);              \
     } else {                                                                                   \
       if ((st_ = allow_big_lds((const void*)k_eam_density_f64<LANES, EVB, TL_, E_>, lds_d)))     \
         return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f64<LANES, EVB, TL_, E_>), grid, block, \
                       lds_d, st, b, (double4*)pos, nl.neigh, nl.nneigh, npad, rtab, etab, g,   \
-                      rc2, saved, partial, rec, ev, ev_cap, ctl);                              \
+                      rc2, saved, partial, rec, ev, ev_cap, 0, ctl);                           \
     }                                                                                          \
     if constexpr (std::is_same<R, float>::value) {                                             \
       if ((st_ = allow_big_lds((const void*)k_eam_force_f32<LANES, EVB, TL_, E_>, lds_f)))       \
@@ -991,9 +1007,9 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
   } while (0)
   const bool big = md_big_list(nl, npad);
   int st_ = MD_OK;
-  if (rec)
+  if (rec && !dr.rec_current)
     hipLaunchKernelGGL(k_fix_records, dim3(md_atom_grid(b.n_tiles)), dim3(MD_ATOM_BLOCK), 0, st, b,
-                       (const double4*)pos, rec);
+                       (const double4*)pos, rec, dr.rec_in ? ctl : nullptr);
 #define MD_EAM_LAUNCH_E(EVB, TL_)                      \
   do {                                                 \
     if (big) MD_EAM_LAUNCH(EVB, TL_, uint64_t);        \
@@ -1015,7 +1031,8 @@ template <typename R, int LANES>
 void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nlist& nl,
                void* force, double* vel, double inv_mass, double half_dt, const DriftArgs& dr,
                long long* ev, int ev_cap, uint4* rec_ws, md_ctl_dev* ctl, hipStream_t st) {
-  uint4* rec = std::is_same<R, float>::value ? rec_ws : nullptr;  // FP32: fixed-point records
+  // FP32: fixed-point records, carried over (md_drift.rec_in) or in the workspace
+  uint4* rec = std::is_same<R, float>::value ? (dr.rec_in ? dr.rec_in : rec_ws) : nullptr;
   LJc c;
   c.sig2 = p.sigma * p.sigma;
   c.eps4 = 4.0 * p.eps;
@@ -1031,10 +1048,11 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
   MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, EVB, E_>), grid, block, 0, st, b,             \
                   (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,      \
                   inv_mass, half_dt, dr, rec, ev, ev_cap, ctl)
-  if (rec)
+  if (rec && !dr.rec_current)
     hipLaunchKernelGGL(k_fix_records, dim3(md_atom_grid(b.n_tiles)), dim3(MD_ATOM_BLOCK), 0, st, b,
-                       (const double4*)pos, rec);
-  hipLaunchKernelGGL(k_lj_prologue, dim3(1), dim3(1024), 0, st, b, ev, ev_cap, ctl);
+                       (const double4*)pos, rec, dr.rec_in ? ctl : nullptr);
+  hipLaunchKernelGGL(k_lj_prologue, dim3(1), dim3(1024), 0, st, b, ev, ev_cap,
+                     rec ? dr.rec_current : 0, ctl);
   if (ev) {
     if (big) MD_LJ_LAUNCH(true, uint64_t);
     else MD_LJ_LAUNCH(true, uint32_t);
@@ -1060,8 +1078,10 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
 // grid must fit the control block's displacement slots.
 static int drift_load(const md_batch* b, const md_nlist* nl, const double* pos, double* vel,
                       double half_dt, const md_drift* drift, DriftArgs* dr) {
-  *dr = DriftArgs{nullptr, nullptr, 0.0, -1.0, md_walls_dev{0, 2, 0.0, 0.0, 0.0}};
+  *dr = DriftArgs{nullptr, nullptr, 0.0, -1.0, md_walls_dev{0, 2, 0.0, 0.0, 0.0}, nullptr, nullptr,
+                  0};
   if (!drift) return MD_OK;
+  if (drift->rec_in && drift->rec_in == drift->rec_out) return MD_ERR_ARG;
   if (!vel || !(half_dt > 0.0) || !drift->pos_out || !drift->pos_ref ||
       drift->pos_out == pos || !isfinite(drift->dt) || half_dt != 0.5 * drift->dt)
     return MD_ERR_ARG;
@@ -1070,6 +1090,9 @@ static int drift_load(const md_batch* b, const md_nlist* nl, const double* pos, 
   dr->pos_ref = drift->pos_ref;
   dr->dt = drift->dt;
   dr->thr2 = drift->half_skin < 0.0 ? -1.0 : drift->half_skin * drift->half_skin;
+  dr->rec_in = (uint4*)drift->rec_in;
+  dr->rec_out = (uint4*)drift->rec_out;
+  dr->rec_current = drift->rec_in && drift->rec_current ? 1 : 0;
   const int tpb = block_threads(*nl) / (64 * nl->lanes);
   if (md_grid_blocks((b->n_tiles + tpb - 1) / tpb) > MD_DMAX_SLOTS) return MD_ERR_ARG;
   return MD_OK;

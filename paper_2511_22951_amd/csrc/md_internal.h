@@ -28,7 +28,9 @@ struct md_ctl_dev {
   int max_nneigh;
   int n_dmax;      // valid entries in dmax[] (0 right after a rebuild)
   int step_next;   // step + 1, published by the kick-drift
-  int pad;
+  int rec_stale;   // 1: positions changed since the last force pass other than by its fused
+                   // kick-drift (md_ctl_init, md_bin_cells, md_verlet_step's drift), so FP32
+                   // neighbour records carried over in md_drift.rec_in must be remade
   double thr2;     // (half skin)^2 of the last kick-drift; < 0: no criterion
   double pad2;
   double dmax[MD_DMAX_SLOTS];  // per-block max |x - x_ref|^2 of the last drift
@@ -51,12 +53,16 @@ __device__ __forceinline__ void md_flag(md_ctl_dev* ctl, int bits);
 // value the kick-drift published, and verify the neighbour list: if an atom has
 // moved more than half the skin since the list was built and no rebuild followed,
 // the list may miss pairs (MD_FLAG_STALE_LIST).
-__device__ __forceinline__ void md_step_bookkeeping(md_ctl_dev* ctl) {
+// verify_rec: the call was told its carried FP32 neighbour records are current (no records
+// kernel ran); a stale flag then marks the step void (MD_FLAG_STALE_RECORDS).
+__device__ __forceinline__ void md_step_bookkeeping(md_ctl_dev* ctl, bool verify_rec = false) {
   if (blockIdx.x != 0) return;
   const bool stale = md_displacement_exceeded(ctl);
   if (threadIdx.x == 0) {
     if (stale) md_flag(ctl, MD_FLAG_STALE_LIST);
+    if (verify_rec && ctl->rec_stale) md_flag(ctl, MD_FLAG_STALE_RECORDS);
     ctl->step = ctl->step_next;
+    ctl->rec_stale = 0;  // this pass's records are made (the records kernel ran before it)
   }
 }
 

@@ -254,7 +254,10 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_bin_copyback(
     double4* pos, double* vel, int* id, double* pos_ref, md_ctl_dev* ctl) {
   if (skip_rebuild(mode, ctl)) return;
   const int n = b.n_atoms;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->n_dmax = 0;  // displacements now measured afresh
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->n_dmax = 0;      // displacements now measured afresh
+    ctl->rec_stale = 1;   // atoms reordered: carried-over neighbour records are void
+  }
   FOR_ATOMS(b, i, T, {
     const double4 p = pos_s[i];
     pos[i] = p;

@@ -18,6 +18,7 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_kick_drift(
   const int n = b.n_atoms;
   const int step = ctl->step + 1;
   const double t_new = (double)step * dt;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->rec_stale = 1;  // positions move here
   const double c = half_dt * inv_mass * MD_ACCEL;
   double d2max = 0.0;
   int bad = 0;

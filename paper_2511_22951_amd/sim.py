@@ -72,12 +72,18 @@ def fused_grid_fits(n_tiles, lanes, block=0):
 class Simulation:
     def __init__(self, system, precision=N.MD_FP64, lanes=4, max_neigh=128, ev_cap=1024,
                  device="cuda", table=None, rebuild_every=0, fused=False, thermostat=None,
-                 block=0):
+                 block=0, carry_records=True):
+        """carry_records: in fused FP32 runs, the fused kick-drift writes the next step's
+        neighbour records (md_drift.rec_out) and the next force call takes them (rec_in)
+        instead of converting the positions again; False converts every step."""
         self.sys = system
         # the Langevin update runs in the kick-drift kernel, so it is not fused
         self.fused = bool(fused) and system.potential in ("eam", "lj") and thermostat is None
         self.primed = False  # fused: the last force pass already did the next kick-drift
         self.pos_alt = None
+        self.carry = bool(carry_records) and self.fused and precision == N.MD_FP32
+        self.rec = self.rec_alt = None  # carried FP32 records of pos and of pos_alt
+        self.rec_fresh = False  # self.rec holds the records of the current positions
         self.rebuild_every = int(rebuild_every)
         self.n_steps = 0
         self.precision = precision
@@ -145,6 +151,7 @@ class Simulation:
 
     def rebuild(self):
         """Rebuild the cell order and the list now (e.g. when switching rebuild policy)."""
+        self.rec_fresh = False
         md.md_bin_cells(self.state, N.MD_ALWAYS)
         md.md_build_neighbors(self.state, self.nl, N.MD_ALWAYS)
 
@@ -159,20 +166,30 @@ class Simulation:
     def step(self, ev=True):
         st = self.state
         if not self.primed:
+            self.rec_fresh = False
             md.md_verlet_step(st, N.MD_KICK_DRIFT, self.dt, self.inv_mass, self.walls,
                               self.half_skin, langevin=self.langevin)
         k = self.rebuild_every
         if k <= 0:
+            self.rec_fresh = False  # the device decides whether the atoms are reordered
             md.md_bin_cells(st, N.MD_IF_FLAGGED)
             md.md_build_neighbors(st, self.nl, N.MD_IF_FLAGGED)
         elif (self.n_steps + 1) % k == 0:
+            self.rec_fresh = False
             md.md_bin_cells(st, N.MD_ALWAYS)
             md.md_build_neighbors(st, self.nl, N.MD_ALWAYS)
         if self.fused:
             if self.pos_alt is None:
                 self.pos_alt = torch.empty_like(st.pos)
+            if self.carry and self.rec is None:
+                # contents need not be valid: md_ctl_init and the first kick-drift mark the
+                # positions as changed, so the first force call converts them
+                self.rec = torch.empty(16 * max(1, st.n), dtype=torch.uint8, device=st.pos.device)
+                self.rec_alt = torch.empty_like(self.rec)
+            # records known current: no conversion launch at all (verified on the device)
             drift = md.drift_params(self.pos_alt, st.pos_ref, self.dt, self.half_skin,
-                                    self.walls)
+                                    self.walls, rec_in=self.rec, rec_out=self.rec_alt,
+                                    rec_current=self.carry and self.rec_fresh)
             if self.pot is None:
                 md.md_lj_forces(st, self.lj, self.nl, self.inv_mass, 0.5 * self.dt, kick=True,
                                 ev=self.ev if ev else None, ev_cap=self.ev_cap, drift=drift)
@@ -181,6 +198,9 @@ class Simulation:
                                  0.5 * self.dt, kick=True, ev=self.ev if ev else None,
                                  ev_cap=self.ev_cap, drift=drift)
             st.pos, self.pos_alt = self.pos_alt, st.pos
+            if self.carry:
+                self.rec, self.rec_alt = self.rec_alt, self.rec
+                self.rec_fresh = True
             self.primed = True
         else:
             self.forces(kick=True, ev=ev)

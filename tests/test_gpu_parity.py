@@ -308,6 +308,55 @@ def test_fused_kick_drift_equals_separate(mdmod, prec, policy):
     assert np.array_equal(a.state.velocities(), b.state.velocities())
 
 
+@pytest.mark.parametrize("pot,policy,graph", [("eam", 0, 0), ("eam", 6, 6), ("lj", 0, 0),
+                                              ("lj", 5, 10)])
+def test_carried_fp32_records_equal_converted(mdmod, pot, policy, graph):
+    """FP32 neighbour records written by the fused kick-drift (md_drift.rec_out) and taken by
+    the next force call (rec_in) give the same bits as converting the positions every step,
+    across rebuilds (which reorder the atoms, so the records are remade), with threshold or
+    fixed-period rebuilds (between which the records are declared current and no conversion is
+    launched), eager or graph-replayed; rec_in equal to rec_out is refused, and records declared
+    current after a reorder raise MD_ERR_STALE_RECORDS."""
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd.sim import Simulation
+    if pot == "eam":
+        s = mi.eam_copper(cells=6)
+    else:
+        s = mi.lj_argon(cells=4)
+        s.vel = s.vel * np.sqrt(3.0)  # 300 K
+    a = Simulation(s, precision=1, lanes=2, rebuild_every=policy, fused=True,
+                   carry_records=False).setup()
+    b = Simulation(s, precision=1, lanes=2, rebuild_every=policy, fused=True).setup()
+    assert b.carry and not a.carry
+    a.run(30, graph_steps=graph)
+    b.run(30, graph_steps=graph)
+    ia, ib = a.state.check_flags(), b.state.check_flags()
+    assert ia["n_rebuilds"] == ib["n_rebuilds"] >= (1 if policy == 0 and pot == "lj" else 2)
+    assert np.array_equal(a.state.positions(), b.state.positions())
+    assert np.array_equal(a.state.velocities(), b.state.velocities())
+    assert np.array_equal(a.energies(range(31)), b.energies(range(31)))
+    st = b.state
+    drift = mdmod.drift_params(b.pos_alt, st.pos_ref, b.dt, b.half_skin, b.walls,
+                               rec_in=b.rec, rec_out=b.rec)
+    def force(drift):
+        if pot == "eam":
+            mdmod.md_eam_forces(st, b.pot, b.nl, b.table, None, b.inv_mass, 0.5 * b.dt, kick=True,
+                                drift=drift)
+        else:
+            mdmod.md_lj_forces(st, b.lj, b.nl, b.inv_mass, 0.5 * b.dt, kick=True, drift=drift)
+    with pytest.raises(mdmod.MDError) as e:
+        force(drift)
+    assert e.value.status == N.MD_ERR_ARG
+    # records declared current right after a reorder: the device notices, the step is void
+    mdmod.md_bin_cells(st, N.MD_ALWAYS)
+    mdmod.md_build_neighbors(st, b.nl, N.MD_ALWAYS)
+    force(mdmod.drift_params(b.pos_alt, st.pos_ref, b.dt, b.half_skin, b.walls, rec_in=b.rec,
+                             rec_out=b.rec_alt, rec_current=True))
+    with pytest.raises(mdmod.MDError) as e:
+        st.check_flags()
+    assert e.value.status == N.MD_ERR_STALE_RECORDS
+
+
 @pytest.mark.parametrize("fused,k,steps", [(True, 5, 23), (True, 6, 20), (False, 5, 23)])
 def test_graph_only_timed_run_equals_eager(mdmod, fused, k, steps):
     """The benchmark's timed region (Simulation.prepare_timed / replay_timed): a main graph
