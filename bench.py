@@ -70,13 +70,14 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_force_bytes(n_atoms, mean_neigh, force_bytes, fused=False):
+def algorithmic_force_bytes(n_atoms, mean_neigh, force_bytes, fused=False, records=False):
     """EAM force pass, per atom: list length 4 B + list 4 B/entry + own record (x, y, z,
     F') 32 B + force write 3 * force_bytes + velocity read and write 48 B (trailing kick);
     with the next kick-drift fused in, also the displacement reference read 24 B and the
-    new position record written 32 B.  Neighbour records are gathered from cache (counted
-    in the traffic measurement)."""
-    extra = 56.0 if fused else 0.0
+    new position record written 32 B, and when it also writes the next step's FP32
+    neighbour records (carried records), 16 B more.  Neighbour records are gathered from
+    cache (counted in the traffic measurement)."""
+    extra = (56.0 if fused else 0.0) + (16.0 if records else 0.0)
     return n_atoms * (4.0 + 4.0 * mean_neigh + 32.0 + 3.0 * force_bytes + 48.0 + extra)
 
 
@@ -305,6 +306,7 @@ def run_path(system, prec, lanes, args, k_cap=None):
         "kernels_ms": kt, "mean_neigh": nneigh, "max_nneigh": info["max_nneigh"], "f0": f0,
         "lanes": lanes, "rebuild_every": k, "rebuild_ms": rebuild_ms,
         "replay_ms_per_step": per_replay,
+        "records_carried": bool(sim.carry and sim.rebuild_every > 0),
     }
 
 
@@ -457,7 +459,7 @@ def main():
         r = results[name]
         kt = r["kernels_ms"]["eam_force"][0] * 1e-3
         nbytes = algorithmic_force_bytes(n, r["mean_neigh"], 4 if name == "fp32" else 8,
-                                         fused=not args.unfused)
+                                         fused=not args.unfused, records=r["records_carried"])
         a = nbytes / kt / 1e9
         vi = measured_valu(name, r["lanes"])
         valu = None if vi is None else {
@@ -505,6 +507,9 @@ def main():
                     "ms_per_step": r["ms"] / args.steps, "lanes": r["lanes"],
                     "rebuilds": r["rebuilds"], "mean_neigh": r["mean_neigh"],
                     "kick_drift": "fused into the force pass" if not args.unfused else "own pass",
+                    "records": ("carried: written by the fused kick-drift, no conversion "
+                                "between rebuilds" if r["records_carried"] else
+                                ("converted every step" if k == "fp32" else "none (FP64)")),
                     "rebuild_policy": ("every %d steps (4/5 of the shortest interval of a %d-step "
                                        "warm-up on the threshold), half-skin criterion verified "
                                        "every step (no violation; %d void runs repeated)"

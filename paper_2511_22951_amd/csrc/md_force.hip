@@ -755,6 +755,8 @@ __device__ __forceinline__ void eam_force_body(
     __syncthreads();
     accumulate_record(b, TPB, lb, nlb, tsum, ev + (size_t)(ctl->step % ev_cap) * b.n_rep * MD_EV_LEN);
   }
+  // positions move without new records: carried records are void from here on
+  if (dr.pos_out && !dr.rec_out && blockIdx.x == 0 && threadIdx.x == 0) ctl->rec_stale = 1;
   if (dr.pos_out) md_publish_dmax(d2max, bad, dr.thr2, ctl);
 }
 
@@ -900,6 +902,8 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
     accumulate_record(b, TPB, lb, nlb, tsum,
                            ev + (size_t)(ctl->step % ev_cap) * b.n_rep * MD_EV_LEN);
   }
+  // positions move without new records: carried records are void from here on
+  if (dr.pos_out && !dr.rec_out && blockIdx.x == 0 && threadIdx.x == 0) ctl->rec_stale = 1;
   if (dr.pos_out) md_publish_dmax(d2max, bad, dr.thr2, ctl);
 }
 

@@ -73,9 +73,11 @@ class Simulation:
     def __init__(self, system, precision=N.MD_FP64, lanes=4, max_neigh=128, ev_cap=1024,
                  device="cuda", table=None, rebuild_every=0, fused=False, thermostat=None,
                  block=0, carry_records=True):
-        """carry_records: in fused FP32 runs, the fused kick-drift writes the next step's
-        neighbour records (md_drift.rec_out) and the next force call takes them (rec_in)
-        instead of converting the positions again; False converts every step."""
+        """carry_records: in fused FP32 runs with fixed-period rebuilds, the fused kick-drift
+        writes the next step's neighbour records (md_drift.rec_out) and the next force call
+        takes them (rec_in) instead of converting the positions again, with no conversion
+        launch between rebuilds; False (and threshold rebuilds, where the device decides
+        whether the atoms are reordered) converts every step."""
         self.sys = system
         # the Langevin update runs in the kick-drift kernel, so it is not fused
         self.fused = bool(fused) and system.potential in ("eam", "lj") and thermostat is None
@@ -181,15 +183,19 @@ class Simulation:
         if self.fused:
             if self.pos_alt is None:
                 self.pos_alt = torch.empty_like(st.pos)
-            if self.carry and self.rec is None:
+            carry = self.carry and self.rebuild_every > 0
+            if not carry:
+                self.rec_fresh = False
+            elif self.rec is None:
                 # contents need not be valid: md_ctl_init and the first kick-drift mark the
                 # positions as changed, so the first force call converts them
                 self.rec = torch.empty(16 * max(1, st.n), dtype=torch.uint8, device=st.pos.device)
                 self.rec_alt = torch.empty_like(self.rec)
             # records known current: no conversion launch at all (verified on the device)
             drift = md.drift_params(self.pos_alt, st.pos_ref, self.dt, self.half_skin,
-                                    self.walls, rec_in=self.rec, rec_out=self.rec_alt,
-                                    rec_current=self.carry and self.rec_fresh)
+                                    self.walls, rec_in=self.rec if carry else None,
+                                    rec_out=self.rec_alt if carry else None,
+                                    rec_current=carry and self.rec_fresh)
             if self.pot is None:
                 md.md_lj_forces(st, self.lj, self.nl, self.inv_mass, 0.5 * self.dt, kick=True,
                                 ev=self.ev if ev else None, ev_cap=self.ev_cap, drift=drift)
@@ -198,7 +204,7 @@ class Simulation:
                                  0.5 * self.dt, kick=True, ev=self.ev if ev else None,
                                  ev_cap=self.ev_cap, drift=drift)
             st.pos, self.pos_alt = self.pos_alt, st.pos
-            if self.carry:
+            if carry:
                 self.rec, self.rec_alt = self.rec_alt, self.rec
                 self.rec_fresh = True
             self.primed = True

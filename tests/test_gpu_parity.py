@@ -327,7 +327,7 @@ def test_carried_fp32_records_equal_converted(mdmod, pot, policy, graph):
     a = Simulation(s, precision=1, lanes=2, rebuild_every=policy, fused=True,
                    carry_records=False).setup()
     b = Simulation(s, precision=1, lanes=2, rebuild_every=policy, fused=True).setup()
-    assert b.carry and not a.carry
+    assert b.carry and not a.carry  # b carries its records when rebuilds have a fixed period
     a.run(30, graph_steps=graph)
     b.run(30, graph_steps=graph)
     ia, ib = a.state.check_flags(), b.state.check_flags()
@@ -336,8 +336,11 @@ def test_carried_fp32_records_equal_converted(mdmod, pot, policy, graph):
     assert np.array_equal(a.state.velocities(), b.state.velocities())
     assert np.array_equal(a.energies(range(31)), b.energies(range(31)))
     st = b.state
+    r1 = torch.empty(16 * st.n, dtype=torch.uint8, device="cuda")
+    r2 = torch.empty_like(r1)
     drift = mdmod.drift_params(b.pos_alt, st.pos_ref, b.dt, b.half_skin, b.walls,
-                               rec_in=b.rec, rec_out=b.rec)
+                               rec_in=r1, rec_out=r1)
+
     def force(drift):
         if pot == "eam":
             mdmod.md_eam_forces(st, b.pot, b.nl, b.table, None, b.inv_mass, 0.5 * b.dt, kick=True,
@@ -350,11 +353,33 @@ def test_carried_fp32_records_equal_converted(mdmod, pot, policy, graph):
     # records declared current right after a reorder: the device notices, the step is void
     mdmod.md_bin_cells(st, N.MD_ALWAYS)
     mdmod.md_build_neighbors(st, b.nl, N.MD_ALWAYS)
-    force(mdmod.drift_params(b.pos_alt, st.pos_ref, b.dt, b.half_skin, b.walls, rec_in=b.rec,
-                             rec_out=b.rec_alt, rec_current=True))
+    force(mdmod.drift_params(b.pos_alt, st.pos_ref, b.dt, b.half_skin, b.walls, rec_in=r1,
+                             rec_out=r2, rec_current=True))
     with pytest.raises(mdmod.MDError) as e:
         st.check_flags()
     assert e.value.status == N.MD_ERR_STALE_RECORDS
+
+
+def test_carried_records_after_steps_without_them(mdmod):
+    """Fused FP32 steps that write no records, between steps that carry them: those force
+    passes mark the carried buffers stale on the device, so the next carried step (which does
+    not claim its records current) converts again -- the run equals one that converts every
+    step, bit for bit."""
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.eam_copper(cells=6)
+    a = Simulation(s, precision=1, lanes=2, rebuild_every=6, fused=True,
+                   carry_records=False).setup()
+    b = Simulation(s, precision=1, lanes=2, rebuild_every=6, fused=True).setup()
+    a.run(20)
+    b.run(7)
+    b.carry = False  # steps 8-10 move the atoms without writing records
+    b.run(3)
+    b.carry = True   # step 11 is no rebuild step: only the device's mark makes it convert
+    b.run(10)
+    assert np.array_equal(a.state.positions(), b.state.positions())
+    assert np.array_equal(a.state.velocities(), b.state.velocities())
+    a.state.check_flags()
+    b.state.check_flags()
 
 
 @pytest.mark.parametrize("fused,k,steps", [(True, 5, 23), (True, 6, 20), (False, 5, 23)])
