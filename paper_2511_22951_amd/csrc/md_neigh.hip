@@ -79,29 +79,23 @@ _Pragma("unroll")
     const int cell = D.cell_off + (c[0] * D.nc[1] + c[1]) * D.nc[2] + c[2];
     pos[i] = make_double4(x[0], x[1], x[2], p.w);
     cell_of[i] = cell;
-    // Histogram with one atomic per distinct cell of the wavefront (the atoms are
-    // still nearly in cell order from the last rebuild); each atom keeps the slot
-    // it got, so the scatter needs no atomics.  Slot order inside a cell is
-    // arbitrary here; the gather ranks by id.
+    // Histogram with one atomic per run of equal cells among the wavefront's atoms
+    // (they are still nearly in cell order from the last rebuild), all runs' atomics
+    // in one instruction; each atom keeps the slot it got, so the scatter needs no
+    // atomics.  Slot order inside a cell is arbitrary here; the gather ranks by id.
+    // The active lanes of a tile are lanes 0 .. count - 1.
     const int lane = threadIdx.x & (MD_WAVE - 1);
-    bool done = false;
-    int rank = 0;
-    for (;;) {
-      const unsigned long long pend = __builtin_amdgcn_ballot_w64(!done);
-      if (pend == 0) break;
-      const int leader = __builtin_ctzll(pend);
-      const int lc = __shfl(cell, leader, MD_WAVE);
-      const bool mine = !done && cell == lc;
-      const unsigned long long m = __builtin_amdgcn_ballot_w64(mine);
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&counts[lc], (int)__popcll(m));
-      base = __shfl(base, leader, MD_WAVE);
-      if (mine) {
-        rank = base + lanes_below(m);
-        done = true;
-      }
+    const int prev = __shfl(cell, lane > 0 ? lane - 1 : 0, MD_WAVE);
+    const unsigned long long leads = __builtin_amdgcn_ballot_w64(lane == 0 || prev != cell);
+    const int start = 63 - __builtin_clzll(leads & ((2ull << lane) - 1));  // this run's first lane
+    int base = 0;
+    if (lane == start) {
+      const unsigned long long later = leads & ~((2ull << lane) - 1);
+      const int end = later ? __builtin_ctzll(later) : T.count;
+      base = atomicAdd(&counts[cell], end - lane);
     }
-    rank_of[i] = rank;
+    base = __shfl(base, start, MD_WAVE);
+    rank_of[i] = base + (lane - start);
   });
   if (bad) md_flag(ctl, bad);
 }
@@ -145,9 +139,11 @@ __global__ __launch_bounds__(1024) void k_scan_one(int n_cells, int mode, int* c
   const int per = (n_cells + 1023) / 1024;
   const int beg = min(n_cells, (int)threadIdx.x * per), end = min(n_cells, beg + per);
   int v = 0;
+#pragma unroll 8
   for (int k = beg; k < end; ++k) v += counts[k];
   int total;
   int run = block_incl_scan(v, s_w, total) - v;
+#pragma unroll 8
   for (int k = beg; k < end; ++k) {
     const int c = counts[k];
     cell_start[k] = run;
