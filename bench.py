@@ -749,8 +749,10 @@ def bench_lj_paper(args):
 
 def bench_nvt(args):
     """EAM Cu 131,072 atoms, FP32-mixed forces, NVT: the Langevin update of the whole box
-    (300 K, stiffness 0.5/ps as in Secs. 3.2-3.3) in the kick-drift kernel, lists rebuilt
-    every 9 steps; beside the same run without the thermostat (kick-drift unfused in both)."""
+    (300 K, stiffness 0.5/ps as in Secs. 3.2-3.3) before every half kick, lists rebuilt
+    every 9 steps; beside the same run without the thermostat.  The kick-drift (with the
+    Langevin update) is fused into the force pass, as in the NVE benchmark; --unfused runs
+    it as its own kernel in both runs."""
     import torch
     import mdinputs as mi
     from paper_2511_22951_amd import _native as N
@@ -760,14 +762,17 @@ def bench_nvt(args):
     n = system.pos.shape[0]
     steps = args.steps or 1000
     k = args.rebuild_every if args.rebuild_every > 0 else 9
-    gs = max(2 * k, args.graph_steps // k * k)
+    fused = not args.unfused
+    period = 2 * k if fused and k % 2 else k
+    gs = max(2 * period, args.graph_steps // period * period)
     lanes = args.lanes or autotune_lanes(system, N.MD_FP32)
     lang = {"seed": 2511, "regions": [{"T": 300.0, "gamma": 0.5}]}
     res = {}
+    kname = "eam_force" if fused else "kick_drift"
     for name, thermo in (("nvt", lang), ("nve", None)):
         cap = args.warmup + steps + args.kernel_samples + 2 * gs + 64
         sim = Simulation(system, precision=N.MD_FP32, lanes=lanes, ev_cap=cap, rebuild_every=k,
-                         thermostat=thermo).setup()
+                         thermostat=thermo, fused=fused).setup()
         sim.run(args.warmup, graph_steps=gs)
         torch.cuda.synchronize()
         st0 = sim.state.read_flags()[1]
@@ -776,15 +781,26 @@ def bench_nvt(args):
         N.check(status, "device flags after the timed run")
         ev = sim.energies(range(info["step"] - steps + 1, info["step"] + 1))
         temps = 2.0 * ev[:, 7] / ((3 * n - 3) * 8.617333262e-5)
-        kd = time_kernel(N, "kick_drift", lambda: sim.step(), args.kernel_samples)[0]
+        kt = time_kernel(N, kname, lambda: sim.step(), args.kernel_samples)[0]
+        nn = sim.nl.lengths().double().mean().item()
         res[name] = {"atom_steps_per_s": n * steps / (ms * 1e-3), "ms_per_step": ms / steps,
-                     "kick_drift_us": 1e3 * kd, "mean_T_K": float(temps.mean()),
-                     "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"]}
+                     kname + "_us": 1e3 * kt, "mean_T_K": float(temps.mean()),
+                     "rebuilds": info["n_rebuilds"] - st0["n_rebuilds"], "mean_neigh": nn,
+                     "kick_drift": "fused into the force pass" if fused else "own kernel"}
         del sim
-    # kick-drift traffic per atom: read v 24, f 12, x 32, x_ref 24 (and id 4 with the
-    # thermostat); write v 24, x 32
-    kd_bytes = n * (148.0 + 4.0)
-    achieved = kd_bytes / (res["nvt"]["kick_drift_us"] * 1e-6) / 1e9
+    if fused:
+        # the force pass with the kick-drift fused in (and the next step's FP32 records),
+        # plus the atom id the thermostat reads
+        nbytes = algorithmic_force_bytes(n, res["nvt"]["mean_neigh"], 4, fused=True,
+                                         records=True) + 4.0 * n
+        kernel = "k_eam_force_f32 (Langevin update and kick-drift fused)"
+    else:
+        # kick-drift traffic per atom: read v 24, f 12, x 32, x_ref 24 (and id 4 with the
+        # thermostat); write v 24, x 32
+        nbytes = n * (148.0 + 4.0)
+        kernel = "k_kick_drift (Langevin)"
+    kus = res["nvt"][kname + "_us"]
+    achieved = nbytes / (kus * 1e-6) / 1e9
     out = {
         "metric": "atom-steps/s (EAM Cu NVT, Langevin thermostat)",
         "value": res["nvt"]["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1,
@@ -794,12 +810,12 @@ def bench_nvt(args):
         "config": {"workload": "EAM Cu fcc 32^3 = 131072 atoms, 300 K, dt 1 fs, skin 0.3, "
                                "Langevin 300 K / 0.5 per ps over the whole box, rebuild every "
                                "%d steps" % k, "n_atoms": n, "lanes_per_atom": lanes,
-                   "graph_steps": gs},
+                   "graph_steps": gs, "fused_kick_drift": fused},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_kick_drift (Langevin)",
-                     "kernel_us": res["nvt"]["kick_drift_us"], "bytes_per_launch": kd_bytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+                     "kernel_us": kus, "bytes_per_launch": nbytes},
         "paths": res,
+        "thermostat_cost": res["nvt"]["ms_per_step"] / res["nve"]["ms_per_step"] - 1.0,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

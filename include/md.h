@@ -318,7 +318,12 @@ int md_build_neighbors(const md_batch* b, md_rebuild_mode mode, const double* po
  * rec_in (no md_bin_cells, md_verlet_step or md_ctl_init in between), so the call does not
  * even launch the check; should the control block say otherwise, the records are still
  * used as they are and MD_FLAG_STALE_RECORDS is raised (md_read_flags then returns
- * MD_ERR_STALE_RECORDS and the step is void). */
+ * MD_ERR_STALE_RECORDS and the step is void).
+ *
+ * langevin (NULL: NVE): the Langevin velocity update of md_verlet_step (NVT, Sec. 1.5)
+ * applied to v(n) before the next half kick, with the random numbers of step n + 1 --
+ * the same operations as md_verlet_step(MD_KICK_DRIFT, ..., langevin) at the start of
+ * step n + 1; MD_ERR_ARG for a malformed md_langevin (as md_verlet_step). */
 #define MD_DRIFT_MAX_BLOCKS 32768
 typedef struct md_drift {
   double* pos_out;
@@ -330,6 +335,7 @@ typedef struct md_drift {
   void* rec_out;         /* FP32 neighbour records of pos_out are written here, or NULL */
   int rec_current;       /* 1: rec_in is known to be current (see above); 0: checked */
   int pad;
+  const md_langevin* langevin; /* thermostat of the next kick, or NULL (see above) */
 } md_drift;
 
 /* Lennard-Jones forces (eq. 1.6), energy and virial.  force is [3][n] FP64 or

@@ -106,7 +106,8 @@ class BPNN(C.Structure):
 class Drift(C.Structure):
     _fields_ = [("pos_out", C.c_void_p), ("pos_ref", C.c_void_p), ("dt", C.c_double),
                 ("half_skin", C.c_double), ("walls", Walls), ("rec_in", C.c_void_p),
-                ("rec_out", C.c_void_p), ("rec_current", C.c_int), ("pad", C.c_int)]
+                ("rec_out", C.c_void_p), ("rec_current", C.c_int), ("pad", C.c_int),
+                ("langevin", C.c_void_p)]
 
 
 _lib = None

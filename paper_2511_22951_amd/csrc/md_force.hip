@@ -377,15 +377,15 @@ __device__ __forceinline__ double write_force_kick(int i, int n, R fx, R fy, R f
   force[2 * n + i] = fz;
   if (!vel) return 0.0;
   const double c = half_dt * inv_mass * MD_ACCEL;
-  const double vx = vel[i] + c * (double)fx;
-  const double vy = vel[n + i] + c * (double)fy;
-  const double vz = vel[2 * n + i] + c * (double)fz;
+  const double vx = md_kick(vel[i], c, (double)fx);
+  const double vy = md_kick(vel[n + i], c, (double)fy);
+  const double vz = md_kick(vel[2 * n + i], c, (double)fz);
   if (half_dt != 0.0) {
     vel[i] = vx;
     vel[n + i] = vy;
     vel[2 * n + i] = vz;
   }
-  return 0.5 / (inv_mass * MD_ACCEL) * (vx * vx + vy * vy + vz * vz);
+  return 0.5 / (inv_mass * MD_ACCEL) * md_norm2(vx, vy, vz);
 }
 
 
@@ -559,15 +559,17 @@ struct DriftArgs {
   uint4* rec_in;   // FP32 records of pos carried over from the last force pass, or nullptr
   uint4* rec_out;  // FP32 records of pos_out written by the fused drift, or nullptr
   int rec_current; // rec_in declared current: no records kernel, verified on the device
+  md_langevin_dev L;  // the Langevin update before the next half kick (L.n = 0: none)
 };
 
 // Epilogue of a force pass with the next kick-drift fused in: write the force, apply
 // the trailing half kick of this step (its kinetic energy is returned), then the next
-// step's half kick and drift with the walls at (step + 1) dt -- the same operations, in
-// the same order, as md_verlet_step(MD_KICK_DRIFT) -- into dr.pos_out; d2max gets the
+// step's Langevin update (NVT) if any, half kick and drift with the walls at (step + 1) dt
+// -- the same operations, in the same order, as md_verlet_step(MD_KICK_DRIFT) -- into
+// dr.pos_out; d2max gets the
 // atom's displacement from x_ref.  In FP32 with dr.rec_out, the new position's fixed-point
 // record (as k_fix_records would make it, in the atom's box D) goes there too.
-template <typename R>
+template <typename R, bool THERMO>
 __device__ __forceinline__ double fused_kick_drift(int i, int n, R fx, R fy, R fz, R* force,
                                                    double* vel, double inv_mass, double half_dt,
                                                    const double4* pos, const DriftArgs& dr,
@@ -578,13 +580,15 @@ __device__ __forceinline__ double fused_kick_drift(int i, int n, R fx, R fy, R f
   force[2 * n + i] = fz;
   const double c = half_dt * inv_mass * MD_ACCEL;
   const double F[3] = {(double)fx, (double)fy, (double)fz};
-  double v[3] = {vel[i] + c * F[0], vel[n + i] + c * F[1], vel[2 * n + i] + c * F[2]};
-  const double ke = 0.5 / (inv_mass * MD_ACCEL) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  v[0] = v[0] + c * F[0];
-  v[1] = v[1] + c * F[1];
-  v[2] = v[2] + c * F[2];
+  double v[3] = {md_kick(vel[i], c, F[0]), md_kick(vel[n + i], c, F[1]),
+                  md_kick(vel[2 * n + i], c, F[2])};
+  const double ke = 0.5 / (inv_mass * MD_ACCEL) * md_norm2(v[0], v[1], v[2]);
   const double4 p = pos[i];
   double x[3] = {p.x, p.y, p.z};
+  if (THERMO) md_langevin_atom(dr.L, D, i, step + 1, x, v);
+  v[0] = md_kick(v[0], c, F[0]);
+  v[1] = md_kick(v[1], c, F[1]);
+  v[2] = md_kick(v[2], c, F[2]);
   md_drift_atom(x, v, dr.dt, dr.w, (double)(step + 1) * dr.dt);
   vel[i] = v[0];
   vel[n + i] = v[1];
@@ -601,7 +605,7 @@ __device__ __forceinline__ double fused_kick_drift(int i, int n, R fx, R fy, R f
   return ke;
 }
 
-template <typename R, int LANES, bool EV, bool TLDS, typename E>
+template <typename R, int LANES, bool EV, bool TLDS, typename E, bool THERMO>
 __device__ __forceinline__ void eam_force_body(
     const md_batch& b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, const TabGeom& g,
@@ -723,7 +727,8 @@ __device__ __forceinline__ void eam_force_body(
   int bad = 0;
   if (i >= 0 && S.l == 0) {
     if (dr.pos_out) {
-      acc[6] = fused_kick_drift<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt, pos,
+      acc[6] = fused_kick_drift<R, THERMO>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass,
+                                           half_dt, pos,
                                    dr, ctl->step, b.domains[T.rep], b.r_ns, d2max, bad);
     } else {
       acc[6] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
@@ -768,16 +773,20 @@ __device__ __forceinline__ void eam_force_body(
       const int* __restrict__ nneigh, int npad, const R* __restrict__ ftab_g, TabGeom g, R rc2, \
       R *force, double *vel, double inv_mass, double half_dt, DriftArgs dr,                     \
       const double *partial, const uint4 *rec, long long *ev, int ev_cap, md_ctl_dev *ctl
-template <int LANES, bool EV, bool TLDS, typename E>
+// THERMO: the fused kick-drift starts with the Langevin update (a kernel of its own, so
+// that the random numbers do not raise the register budget of the NVE kernels).
+template <int LANES, bool EV, bool TLDS, typename E, bool THERMO>
 __global__ __launch_bounds__(FBLOCK) void k_eam_force_f32(
     MD_EAM_FORCE_ARGS(float)) {
-  eam_force_body<float, LANES, EV, TLDS, E>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
-                                         inv_mass, half_dt, dr, partial, rec, ev, ev_cap, ctl);
+  eam_force_body<float, LANES, EV, TLDS, E, THERMO>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2,
+                                                    force, vel, inv_mass, half_dt, dr, partial,
+                                                    rec, ev, ev_cap, ctl);
 }
-template <int LANES, bool EV, bool TLDS, typename E>
+template <int LANES, bool EV, bool TLDS, typename E, bool THERMO>
 __global__ __launch_bounds__(FBLOCK) void k_eam_force_f64(MD_EAM_FORCE_ARGS(double)) {
-  eam_force_body<double, LANES, EV, TLDS, E>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2, force, vel,
-                                          inv_mass, half_dt, dr, partial, nullptr, ev, ev_cap, ctl);
+  eam_force_body<double, LANES, EV, TLDS, E, THERMO>(b, pos, neigh, nneigh, npad, ftab_g, g, rc2,
+                                                     force, vel, inv_mass, half_dt, dr, partial,
+                                                     nullptr, ev, ev_cap, ctl);
 }
 #undef MD_EAM_FORCE_ARGS
 
@@ -798,7 +807,7 @@ struct LJc {
   double sig2, eps4, eps24, ucut;
 };
 
-template <typename R, int LANES, bool EV, typename E>
+template <typename R, int LANES, bool EV, typename E, bool THERMO>
 __global__ __launch_bounds__(FBLOCK) void k_lj(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, LJc c, R rc2, R* force, double* vel,
@@ -883,7 +892,8 @@ __global__ __launch_bounds__(FBLOCK) void k_lj(
   int bad = 0;
   if (i >= 0 && S.l == 0) {
     if (dr.pos_out)
-      acc[7] = fused_kick_drift<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt, pos,
+      acc[7] = fused_kick_drift<R, THERMO>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass,
+                                           half_dt, pos,
                                    dr, ctl->step, b.domains[T.rep], b.r_ns, d2max, bad);
     else
       acc[7] = write_force_kick<R>(i, b.n_atoms, fx, fy, fz, force, vel, inv_mass, half_dt);
@@ -978,7 +988,7 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
   const bool ld = table_in_lds<R>(rows, MD_RTAB_W);
   const size_t lds_d = ld ? (size_t)rows * MD_RTAB_W * sizeof(R) : 0;
   const size_t lds_f = ld ? (size_t)rows * MD_FTAB_W * sizeof(R) : 0;
-#define MD_EAM_LAUNCH(EVB, TL_, E_)                                                               \
+#define MD_EAM_LAUNCH(EVB, TL_, E_, TH_)                                                          \
   do {                                                                                         \
     if constexpr (std::is_same<R, float>::value) {                                             \
       if ((st_ = allow_big_lds((const void*)k_eam_density_f32<LANES, EVB, TL_, E_>, lds_d)))     \
@@ -994,16 +1004,18 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
                       rc2, saved, partial, rec, ev, ev_cap, 0, ctl);                           \
     }                                                                                          \
     if constexpr (std::is_same<R, float>::value) {                                             \
-      if ((st_ = allow_big_lds((const void*)k_eam_force_f32<LANES, EVB, TL_, E_>, lds_f)))       \
+      if ((st_ = allow_big_lds((const void*)k_eam_force_f32<LANES, EVB, TL_, E_, TH_>, lds_f)))  \
         return st_;                                                                            \
-      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f32<LANES, EVB, TL_, E_>), grid, block,     \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f32<LANES, EVB, TL_, E_, TH_>), grid,   \
+                      block,                                                                   \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
                       rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, rec, ev, ev_cap,    \
                       ctl);                                                                    \
     } else {                                                                                   \
-      if ((st_ = allow_big_lds((const void*)k_eam_force_f64<LANES, EVB, TL_, E_>, lds_f)))       \
+      if ((st_ = allow_big_lds((const void*)k_eam_force_f64<LANES, EVB, TL_, E_, TH_>, lds_f)))  \
         return st_;                                                                            \
-      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f64<LANES, EVB, TL_, E_>), grid, block,     \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_FORCE, (k_eam_force_f64<LANES, EVB, TL_, E_, TH_>), grid,   \
+                      block,                                                                   \
                       lds_f, st, b, (const double4*)pos, nl.neigh, nl.nneigh, npad, ftab, g,   \
                       rc2, (R*)force, vel, inv_mass, half_dt, dr, partial, rec, ev, ev_cap,    \
                       ctl);                                                                    \
@@ -1014,10 +1026,15 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
   if (rec && !dr.rec_current)
     hipLaunchKernelGGL(k_fix_records, dim3(md_atom_grid(b.n_tiles)), dim3(MD_ATOM_BLOCK), 0, st, b,
                        (const double4*)pos, rec, dr.rec_in ? ctl : nullptr);
-#define MD_EAM_LAUNCH_E(EVB, TL_)                      \
-  do {                                                 \
-    if (big) MD_EAM_LAUNCH(EVB, TL_, uint64_t);        \
-    else MD_EAM_LAUNCH(EVB, TL_, uint32_t);            \
+#define MD_EAM_LAUNCH_E(EVB, TL_)                                             \
+  do {                                                                        \
+    if (dr.L.n > 0) {                                                         \
+      if (big) MD_EAM_LAUNCH(EVB, TL_, uint64_t, true);                       \
+      else MD_EAM_LAUNCH(EVB, TL_, uint32_t, true);                           \
+    } else {                                                                  \
+      if (big) MD_EAM_LAUNCH(EVB, TL_, uint64_t, false);                      \
+      else MD_EAM_LAUNCH(EVB, TL_, uint32_t, false);                          \
+    }                                                                         \
   } while (0)
   if (ev) {
     if (ld) MD_EAM_LAUNCH_E(true, true);
@@ -1048,10 +1065,15 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
   const dim3 grid(md_grid_blocks((b.n_tiles + TPB - 1) / TPB)), block(bt);
   const int npad = md_npad(b.n_atoms);
   const bool big = md_big_list(nl, npad);
-#define MD_LJ_LAUNCH(EVB, E_)                                                                  \
-  MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, EVB, E_>), grid, block, 0, st, b,             \
+#define MD_LJ_LAUNCH2(EVB, E_, TH_)                                                            \
+  MD_LAUNCH_TIMED(MD_KERNEL_LJ, (k_lj<R, LANES, EVB, E_, TH_>), grid, block, 0, st, b,        \
                   (const double4*)pos, nl.neigh, nl.nneigh, npad, c, rc2, (R*)force, vel,      \
                   inv_mass, half_dt, dr, rec, ev, ev_cap, ctl)
+#define MD_LJ_LAUNCH(EVB, E_)                                                                  \
+  do {                                                                                         \
+    if (dr.L.n > 0) MD_LJ_LAUNCH2(EVB, E_, true);                                              \
+    else MD_LJ_LAUNCH2(EVB, E_, false);                                                        \
+  } while (0)
   if (rec && !dr.rec_current)
     hipLaunchKernelGGL(k_fix_records, dim3(md_atom_grid(b.n_tiles)), dim3(MD_ATOM_BLOCK), 0, st, b,
                        (const double4*)pos, rec, dr.rec_in ? ctl : nullptr);
@@ -1065,6 +1087,7 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
     else MD_LJ_LAUNCH(false, uint32_t);
   }
 #undef MD_LJ_LAUNCH
+#undef MD_LJ_LAUNCH2
 }
 
 }  // namespace
@@ -1081,7 +1104,7 @@ void launch_lj(const md_batch& b, const md_lj& p, const double* pos, const md_nl
 // The fused kick-drift's arguments (shared by the EAM and LJ passes); the force pass
 // grid must fit the control block's displacement slots.
 static int drift_load(const md_batch* b, const md_nlist* nl, const double* pos, double* vel,
-                      double half_dt, const md_drift* drift, DriftArgs* dr) {
+                      double inv_mass, double half_dt, const md_drift* drift, DriftArgs* dr) {
   *dr = DriftArgs{nullptr, nullptr, 0.0, -1.0, md_walls_dev{0, 2, 0.0, 0.0, 0.0}, nullptr, nullptr,
                   0};
   if (!drift) return MD_OK;
@@ -1090,6 +1113,7 @@ static int drift_load(const md_batch* b, const md_nlist* nl, const double* pos, 
       drift->pos_out == pos || !isfinite(drift->dt) || half_dt != 0.5 * drift->dt)
     return MD_ERR_ARG;
   if (md_walls_load(&drift->walls, &dr->w) != MD_OK) return MD_ERR_ARG;
+  if (md_langevin_load(drift->langevin, drift->dt, inv_mass, &dr->L) != MD_OK) return MD_ERR_ARG;
   dr->pos_out = (double4*)drift->pos_out;
   dr->pos_ref = drift->pos_ref;
   dr->dt = drift->dt;
@@ -1119,7 +1143,7 @@ static int eam_forces(const md_batch* b, const md_eam* p, md_precision prec, con
   // FP32 takes 1-8 lanes per atom (16 is not supported)
   if (prec == MD_FP32 && nl->lanes > 8) return MD_ERR_ARG;
   DriftArgs dr;
-  if (drift_load(b, nl, pos, vel, half_dt, drift, &dr) != MD_OK) return MD_ERR_ARG;
+  if (drift_load(b, nl, pos, vel, inv_mass, half_dt, drift, &dr) != MD_OK) return MD_ERR_ARG;
   if (b->n_atoms == 0 || b->n_tiles == 0) return MD_OK;
   const md_table_layout TL = md_table_plan(p, prec);
   hipStream_t st = (hipStream_t)stream;
@@ -1216,7 +1240,7 @@ extern "C" int md_lj_forces(const md_batch* b, const md_lj* p, md_precision prec
   if (ev && ev_cap < 1) return MD_ERR_ARG;
   if (vel && !(inv_mass > 0.0)) return MD_ERR_ARG;
   DriftArgs dr;
-  if (drift_load(b, nl, pos, vel, half_dt, drift, &dr) != MD_OK) return MD_ERR_ARG;
+  if (drift_load(b, nl, pos, vel, inv_mass, half_dt, drift, &dr) != MD_OK) return MD_ERR_ARG;
   if (b->n_atoms == 0 || b->n_tiles == 0) return MD_OK;
   hipStream_t st = (hipStream_t)stream;
   md_ctl_dev* c = (md_ctl_dev*)ctl;

@@ -167,6 +167,10 @@ struct md_langevin_dev {
   double u[MD_MAX_THERMO_REGIONS][3];
 };
 
+// Host form of md_langevin for one time step and mass (md_verlet.hip); a NULL md_langevin
+// gives n = 0 (no thermostat).  MD_ERR_ARG for a malformed one.
+int md_langevin_load(const md_langevin* lg, double dt, double inv_mass, md_langevin_dev* L);
+
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32 -> 64-bit
 // multiplies with the Weyl key schedule.
 __device__ __forceinline__ void md_philox4x32_10(unsigned (&c)[4], unsigned k0, unsigned k1) {
@@ -196,21 +200,24 @@ __device__ __forceinline__ void md_langevin_normals(int id, int step, unsigned k
   const double u0 = ((double)c[0] + 1.0) * s32, u1 = (double)c[1] * s32;
   const double u2 = ((double)c[2] + 1.0) * s32, u3 = (double)c[3] * s32;
   const double r0 = sqrt(-2.0 * log(u0)), r2 = sqrt(-2.0 * log(u2));
-  z[0] = r0 * cos(two_pi * u1);
-  z[1] = r0 * sin(two_pi * u1);
-  z[2] = r2 * cos(two_pi * u3);
+  z[0] = __dmul_rn(r0, cos(two_pi * u1));
+  z[1] = __dmul_rn(r0, sin(two_pi * u1));
+  z[2] = __dmul_rn(r2, cos(two_pi * u3));
 }
 
 // The Langevin velocity update of one atom at position x (start of the step); the
 // region coordinate is folded into the box on a periodic axis, as the wrap of the
-// binning pass does (x - L floor((x - lo) / L), lo + L going to lo).
+// binning pass does (x - L floor((x - lo) / L), lo + L going to lo).  Products are
+// rounded on their own (__dmul_rn: no fused multiply-add), so the separate kick-drift
+// kernel and the force pass that fuses it give the same bits whatever each
+// compilation contracts.
 __device__ __forceinline__ void md_langevin_atom(const md_langevin_dev& L, const md_domain& D,
                                                  int i, int step, const double (&x)[3],
                                                  double (&v)[3]) {
   const int a = L.axis;
   double xa = a == 0 ? x[0] : (a == 1 ? x[1] : x[2]);
   if (D.periodic[a]) {
-    xa = xa - D.len[a] * floor((xa - D.lo[a]) / D.len[a]);
+    xa = xa - __dmul_rn(D.len[a], floor((xa - D.lo[a]) / D.len[a]));
     if (xa >= D.lo[a] + D.len[a]) xa = D.lo[a];
   }
   int r = -1;
@@ -220,7 +227,17 @@ __device__ __forceinline__ void md_langevin_atom(const md_langevin_dev& L, const
   double z[3];
   md_langevin_normals(L.id[i], step, L.key0, L.key1, z);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) v[k] = L.u[r][k] + L.c1[r] * (v[k] - L.u[r][k]) + L.c2[r] * z[k];
+  for (int k = 0; k < 3; ++k)
+    v[k] = (L.u[r][k] + __dmul_rn(L.c1[r], v[k] - L.u[r][k])) + __dmul_rn(L.c2[r], z[k]);
+}
+
+// The integrator's multiply-adds, written as explicit fused operations: the kick
+// v + c F, the drift x + dt v and squared norms are then rounded the same way in every
+// kernel that computes them (the separate kick-drift and the force passes that fuse it),
+// whatever each compilation would contract.
+__device__ __forceinline__ double md_kick(double v, double c, double f) { return fma(c, f, v); }
+__device__ __forceinline__ double md_norm2(double x, double y, double z) {
+  return fma(z, z, fma(y, y, x * x));
 }
 
 // The drift of velocity Verlet for one atom: x <- x + dt v (x holds the old
@@ -230,12 +247,12 @@ __device__ __forceinline__ void md_langevin_atom(const md_langevin_dev& L, const
 // both give the same bits.
 __device__ __forceinline__ void md_drift_atom(double (&x)[3], double (&v)[3], double dt,
                                               const md_walls_dev& w, double t_new) {
-  x[0] = x[0] + dt * v[0];
-  x[1] = x[1] + dt * v[1];
-  x[2] = x[2] + dt * v[2];
+  x[0] = fma(dt, v[0], x[0]);
+  x[1] = fma(dt, v[1], x[1]);
+  x[2] = fma(dt, v[2], x[2]);
   if (w.enabled) {
     const int a = w.axis;
-    const double zp = w.z0 + w.v * t_new;
+    const double zp = fma(w.v, t_new, w.z0);
     if (x[a] < zp) {
       x[a] = 2.0 * zp - x[a];
       v[a] = 2.0 * w.v - v[a];
@@ -252,7 +269,7 @@ __device__ __forceinline__ void md_drift_atom(double (&x)[3], double (&v)[3], do
 __device__ __forceinline__ double md_disp2(const double (&x)[3], const double* pos_ref, int i,
                                            int n) {
   const double dx = x[0] - pos_ref[i], dy = x[1] - pos_ref[n + i], dz = x[2] - pos_ref[2 * n + i];
-  const double d2 = dx * dx + dy * dy + dz * dz;
+  const double d2 = md_norm2(dx, dy, dz);
   return d2 >= 0.0 ? d2 : INFINITY;
 }
 

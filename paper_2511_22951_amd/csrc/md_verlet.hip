@@ -38,13 +38,13 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_kick_drift(
       v[1] = vel[n + i];
       v[2] = vel[2 * n + i];
       md_langevin_atom(L, b.domains[T.rep], i, step, x, v);
-      v[0] = v[0] + c * (double)force[i];
-      v[1] = v[1] + c * (double)force[n + i];
-      v[2] = v[2] + c * (double)force[2 * n + i];
+      v[0] = md_kick(v[0], c, (double)force[i]);
+      v[1] = md_kick(v[1], c, (double)force[n + i]);
+      v[2] = md_kick(v[2], c, (double)force[2 * n + i]);
     } else {
-      v[0] = vel[i] + c * (double)force[i];
-      v[1] = vel[n + i] + c * (double)force[n + i];
-      v[2] = vel[2 * n + i] + c * (double)force[2 * n + i];
+      v[0] = md_kick(vel[i], c, (double)force[i]);
+      v[1] = md_kick(vel[n + i], c, (double)force[n + i]);
+      v[2] = md_kick(vel[2 * n + i], c, (double)force[2 * n + i]);
     }
     md_drift_atom(x, v, dt, w, t_new);
     vel[i] = v[0];
@@ -71,16 +71,16 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_kick(md_batch b, double half_
     const md_tile T = b.tiles[tile];
     if (lane >= T.count) continue;
     const int i = T.first + lane;
-    vel[i] += c * (double)force[i];
-    vel[n + i] += c * (double)force[n + i];
-    vel[2 * n + i] += c * (double)force[2 * n + i];
+    vel[i] = md_kick(vel[i], c, (double)force[i]);
+    vel[n + i] = md_kick(vel[n + i], c, (double)force[n + i]);
+    vel[2 * n + i] = md_kick(vel[2 * n + i], c, (double)force[2 * n + i]);
   }
 }
 
 }  // namespace
 
 // Host form of md_langevin for one time step and mass.
-static int langevin_load(const md_langevin* lg, double dt, double inv_mass, md_langevin_dev* L) {
+int md_langevin_load(const md_langevin* lg, double dt, double inv_mass, md_langevin_dev* L) {
   *L = md_langevin_dev{};
   if (!lg) return MD_OK;
   if (!lg->id || lg->axis < 0 || lg->axis > 2 || lg->n_regions < 1 ||
@@ -134,7 +134,7 @@ extern "C" int md_verlet_step(const md_batch* b, md_verlet_phase phase, double d
   md_walls_dev w;
   if (md_walls_load(walls, &w) != MD_OK) return MD_ERR_ARG;
   md_langevin_dev L;
-  if (langevin_load(lang, dt, inv_mass, &L) != MD_OK) return MD_ERR_ARG;
+  if (md_langevin_load(lang, dt, inv_mass, &L) != MD_OK) return MD_ERR_ARG;
   const double thr2 = half_skin < 0.0 ? -1.0 : half_skin * half_skin;
   md_ctl_dev* c = (md_ctl_dev*)ctl;
 #define MD_KD_LAUNCH(R, TH)                                                                       \

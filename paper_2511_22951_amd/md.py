@@ -288,15 +288,18 @@ def md_lj_forces(st: State, p, nl: NeighborList, inv_mass=0.0, half_dt=0.0, kick
 
 
 def drift_params(pos_out, pos_ref, dt, half_skin, walls=None, rec_in=None, rec_out=None,
-                 rec_current=False):
+                 rec_current=False, langevin=None):
     """md_drift: the next step's kick-drift to fuse into md_lj_forces or md_eam_forces;
     rec_in / rec_out: FP32 neighbour records carried from step to step (uint8 [16 n]
     device tensors, or None); rec_current: rec_in is known to be current (no launch to
-    check it; a wrong claim raises MD_ERR_STALE_RECORDS)."""
+    check it; a wrong claim raises MD_ERR_STALE_RECORDS); langevin: an N.Langevin
+    (langevin_params) for the Langevin update before the next half kick, which the caller
+    keeps alive while the md_drift is in use."""
     w = walls_params(walls) if isinstance(walls, dict) else walls
     return N.Drift(_ptr(pos_out), _ptr(pos_ref), float(dt), float(half_skin),
                    w if w is not None else N.Walls(0, 2, 0.0, 0.0, 0.0), _ptr(rec_in),
-                   _ptr(rec_out), int(bool(rec_current)), 0)
+                   _ptr(rec_out), int(bool(rec_current)), 0,
+                   C.addressof(langevin) if langevin is not None else None)
 
 
 def md_eam_forces(st: State, pot: EAMPotential, nl: NeighborList, table=None, saved=None,

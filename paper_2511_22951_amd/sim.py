@@ -15,8 +15,8 @@ kick-drift ahead: positions x(n + 1), velocities v(n + 1/2) (`previous_positions
 returns x(n)).
 
 With a thermostat ({"seed", "axis", "regions": [{"lo", "hi", "T", "gamma", "u"}]}) the
-kick-drift starts with the Langevin velocity update of md_langevin (NVT, Sec. 1.5);
-the kick-drift is then never fused.
+kick-drift starts with the Langevin velocity update of md_langevin (NVT, Sec. 1.5), in
+the separate kick-drift or in the fused one (md_drift.langevin) alike.
 
 Rebuild policies (both in the paper):
   rebuild_every = 0: on the threshold (Sec. 1.4) -- the rebuild kernels run every
@@ -79,8 +79,7 @@ class Simulation:
         launch between rebuilds; False (and threshold rebuilds, where the device decides
         whether the atoms are reordered) converts every step."""
         self.sys = system
-        # the Langevin update runs in the kick-drift kernel, so it is not fused
-        self.fused = bool(fused) and system.potential in ("eam", "lj") and thermostat is None
+        self.fused = bool(fused) and system.potential in ("eam", "lj")
         self.primed = False  # fused: the last force pass already did the next kick-drift
         self.pos_alt = None
         self.carry = bool(carry_records) and self.fused and precision == N.MD_FP32
@@ -195,7 +194,8 @@ class Simulation:
             drift = md.drift_params(self.pos_alt, st.pos_ref, self.dt, self.half_skin,
                                     self.walls, rec_in=self.rec if carry else None,
                                     rec_out=self.rec_alt if carry else None,
-                                    rec_current=carry and self.rec_fresh)
+                                    rec_current=carry and self.rec_fresh,
+                                    langevin=self.langevin)
             if self.pot is None:
                 md.md_lj_forces(st, self.lj, self.nl, self.inv_mass, 0.5 * self.dt, kick=True,
                                 ev=self.ev if ev else None, ev_cap=self.ev_cap, drift=drift)

@@ -8,6 +8,8 @@ oracle (oracle/thermostat.py), through the C ABI.
   thermalisation          EAM Cu 4000 atoms, 300 K -> 600 K, mean T of the last
                           1000 steps within 3 %
   argument checks         malformed md_langevin -> MD_ERR_ARG
+  fused thermostat        the update in the force pass's fused kick-drift
+                          (md_drift.langevin) equals md_verlet_step's bit for bit
 """
 import ctypes as C
 
@@ -127,3 +129,35 @@ def test_malformed_thermostat_is_rejected():
                           C.byref(md.langevin_params(st, good)), md._ptr(st.pos_ref), -1.0,
                           md._ptr(st.ctl), md._stream())
     assert rc == N.MD_ERR_ARG
+
+
+@pytest.mark.parametrize("pot,prec,policy", [("eam", 0, 0), ("eam", 0, 6), ("eam", 1, 6),
+                                             ("lj", 0, 5)])
+def test_fused_nvt_equals_separate(pot, prec, policy):
+    """The Langevin update fused into the force pass's kick-drift (md_drift.langevin) gives
+    the same bits as md_verlet_step with the thermostat: 30 steps, two slab regions (one
+    with a drift velocity) and a free zone, threshold rebuilds or fixed-period rebuilds with
+    graph replay (FP32 with carried neighbour records); the fused run is one kick-drift
+    ahead at the end."""
+    from paper_2511_22951_amd import _native as N
+    from paper_2511_22951_amd import md
+    from paper_2511_22951_amd.sim import Simulation
+    s = mi.eam_copper(cells=6) if pot == "eam" else mi.lj_argon(cells=4)
+    lz = s.box.len[2]
+    lang = {"seed": 77, "axis": 2, "regions": [
+        {"lo": 0.0, "hi": 0.3 * lz, "T": 500.0, "gamma": 2.0, "u": (0.1, 0.0, 0.0)},
+        {"lo": 0.6 * lz, "hi": lz, "T": 200.0, "gamma": 5.0}]}
+    a = Simulation(s, precision=prec, lanes=4, rebuild_every=policy, thermostat=lang).setup()
+    b = Simulation(s, precision=prec, lanes=4, rebuild_every=policy, thermostat=lang,
+                   fused=True).setup()
+    g = (2 * policy if policy % 2 else policy) if policy else 0
+    a.run(30, graph_steps=g)
+    b.run(30, graph_steps=g)
+    ia, ib = a.state.check_flags(), b.state.check_flags()
+    assert ia["n_rebuilds"] == ib["n_rebuilds"] > 1
+    assert np.array_equal(b.previous_positions(), a.state.positions())
+    assert np.array_equal(a.energies(range(31)), b.energies(range(31)))
+    md.md_verlet_step(a.state, N.MD_KICK_DRIFT, a.dt, a.inv_mass, a.walls, a.half_skin,
+                      langevin=a.langevin)
+    assert np.array_equal(a.state.positions(), b.state.positions())
+    assert np.array_equal(a.state.velocities(), b.state.velocities())
