@@ -15,7 +15,10 @@
 // One kernel visits each atom's list twice (the second visit needs the complete
 // tau_i).  Each wavefront accumulates into its own LDS bins; a block adds its
 // wavefronts' bins in wave order into per-tile partials, and a second kernel
-// adds the tile partials in tile order.  All sums are FP64.
+// adds the tile partials in tile order.  All sums are FP64.  Pair distances crowd
+// around the neighbour shells, so many lanes of one atomic add hit the same phi or
+// rho bin and the LDS serialises them: each wavefront keeps several copies of those
+// bins (lane l adds into copy l mod copies), laid out to start on different banks.
 #include <math.h>
 
 #include "md_internal.h"
@@ -23,6 +26,9 @@
 namespace {
 
 #define MD_ADJ_MAX_BINS 1024
+#define MD_ADJ_U 2        // list entries in flight per lane
+#define MD_ADJ_COPIES 8   // most copies of the phi and rho bins per wavefront
+#define MD_ADJ_LDS 49152  // LDS per block that the copies may fill
 
 __device__ __forceinline__ void bspline_basis(double t, double b[4], double g[4]) {
   const double s = 1.0 - t;
@@ -52,28 +58,87 @@ struct AdjGeom {
   double r_lo, r_inv_h, e_lo, e_inv_h;
   int nr, ne;           // intervals
   int n_phi, n_rho, n_emb, n_bins;
+  int copies, stride;   // copies of a wavefront's phi|rho bins, doubles from one to the next
 };
 
-template <int LANES>
+// 1/sqrt(x) for a normal x > 0: the hardware estimate (about 23 correct bits) refined
+// by two Newton-Raphson steps y <- y + y (1/2 - x y^2 / 2), each of which roughly
+// doubles the correct bits.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-hx * y, y, 0.5), y);
+  return y;
+}
+
+// Interval of x on a uniform grid without the range check: t in [0, 1] inside the
+// clamped interval k (the first visit records the range of u).
+__device__ __forceinline__ int interval_u(double u, int nint, double& t) {
+  const double f = fmin(fmax(floor(u), 0.0), (double)(nint - 1));
+  t = u - f;
+  return (int)f;
+}
+
+// Per-lane list visit with the indices of the next U entries loaded while the
+// records of the current U are in flight (one round trip per U entries).  Entry m
+// of the lane sits U-wise at nb + m * stride; padding past the lane's cnt entries
+// loads the atom itself and is not visited.
+template <int U, typename Load, typename Pair>
+__device__ __forceinline__ void adj_visit(const int* nb, size_t stride, int cnt, int self,
+                                          Load load, Pair pair) {
+  if (cnt <= 0) return;
+  int jn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) jn[u] = nb[u < cnt ? u * stride : 0];
+  for (int b0 = 0; b0 < cnt; b0 += U) {
+    decltype(load(0)) q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = load(b0 + u < cnt ? jn[u] : self);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = b0 + U + u;
+      jn[u] = nb[m < cnt ? m * stride : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (b0 + u < cnt) pair(q[u]);
+  }
+}
+
+struct AdjRec1 {
+  double x, y, z, gx, gy, gz;
+};
+
+// Per pair the basis enters through fixed multiples that are taken out of the
+// loops: 2 beta'_k(t) / h (the factor 1/2 and 1/h go into the per-atom weights) in
+// the first visit and 6 beta_k(t) (the 1/6 goes into c_F'') in the second.
+template <int LANES, int U>
 __global__ __launch_bounds__(64 * LANES) void k_eam_adjoint(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const double* __restrict__ saved,
     const double* __restrict__ G, AdjGeom g, double rc2, double* tile_bins, md_ctl_dev* ctl) {
-  extern __shared__ double bins[];  // [waves][n_bins]
+  // LDS: phi|rho bins [waves][copies][stride], F bins [waves][n_emb], rho coefficients
+  extern __shared__ double bins[];
   const int nw = blockDim.x / MD_WAVE, wid = threadIdx.x / MD_WAVE;
-  for (int q = threadIdx.x; q < nw * g.n_bins; q += blockDim.x) bins[q] = 0.0;
+  const int n_hot = g.n_phi + g.n_rho, n_copy = nw * g.copies;
+  double* emb_bins = bins + (size_t)n_copy * g.stride;
+  double* c_rho = emb_bins + (size_t)nw * g.n_emb;
+  for (int q = threadIdx.x; q < n_copy * g.stride + nw * g.n_emb; q += blockDim.x) bins[q] = 0.0;
+  for (int q = threadIdx.x; q < g.n_rho; q += blockDim.x) c_rho[q] = g.c_rho[q];
   __syncthreads();
   const int t = md_remap_block(b.n_tiles);
   if (t >= b.n_tiles) return;
-  double* wb = bins + (size_t)wid * g.n_bins;
-  double* b_phi = wb;
-  double* b_rho = wb + g.n_phi;
-  double* b_emb = wb + g.n_phi + g.n_rho;
+  double* b_phi = bins + ((size_t)wid * g.copies + (threadIdx.x & (g.copies - 1))) * g.stride;
+  double* b_rho = b_phi + g.n_phi;
+  double* b_emb = emb_bins + (size_t)wid * g.n_emb;
   const md_tile T = b.tiles[t];
   const md_domain& Dm = b.domains[T.rep];
-  const int per[3] = {Dm.periodic[0], Dm.periodic[1], Dm.periodic[2]};
+  // minimum image: a non-periodic axis gets 0 as inverse length (its shift is 0)
   const double len[3] = {Dm.len[0], Dm.len[1], Dm.len[2]};
-  const double inv[3] = {Dm.inv_len[0], Dm.inv_len[1], Dm.inv_len[2]};
+  const double inv[3] = {Dm.periodic[0] ? Dm.inv_len[0] : 0.0,
+                         Dm.periodic[1] ? Dm.inv_len[1] : 0.0,
+                         Dm.periodic[2] ? Dm.inv_len[2] : 0.0};
   const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
   const int n = b.n_atoms;
   bool oor = false;
@@ -83,52 +148,72 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_adjoint(
     const double gix = G[i], giy = G[n + i], giz = G[2 * n + i];
     const double fp = saved[n + i], fpp = saved[2 * n + i];
     const int nn = nneigh[i] & MD_NN_MASK;
+    const int cnt = nn > l ? (nn - l + LANES - 1) / LANES : 0;
     const size_t stride = (size_t)npad * LANES;
-    double tau = 0.0;
     const int* nb = neigh + (size_t)i * LANES + l;
-    for (int m = l; m < nn; m += LANES, nb += stride) {
-      const int j = *nb;
-      const double4 pj = pos[j];
-      double d[3] = {pj.x - pi.x, pj.y - pi.y, pj.z - pi.z};
+    auto disp2 = [&](double x, double y, double z, double d[3]) {
+      d[0] = x - pi.x;
+      d[1] = y - pi.y;
+      d[2] = z - pi.z;
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        if (per[q]) d[q] -= len[q] * rint(d[q] * inv[q]);
-      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      if (!(r2 < rc2)) continue;
-      const double r = sqrt(r2), ir = 1.0 / r;
-      // u_ij = (r_i - r_j) / r = -d / r
-      const double s = -((gix - G[j]) * d[0] + (giy - G[n + j]) * d[1] + (giz - G[2 * n + j]) * d[2]) * ir;
-      double tt, bb[4], gg[4];
-      const int k = interval(r, g.r_lo, g.r_inv_h, g.nr, tt, oor);
-      bspline_basis(tt, bb, gg);
-      double drho = 0.0;
+      for (int q = 0; q < 3; ++q) d[q] = fma(-len[q], rint(d[q] * inv[q]), d[q]);
+      return fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+    };
+    // first visit: w_ij = (G_i - G_j) . (r_j - r_i) / r_ij = -s_ij
+    const double k_phi = 0.25 * g.r_inv_h, k_rho = 0.5 * g.r_inv_h * fp;
+    double tau_w = 0.0, umin = 0.0, umax = 0.0;
+    adj_visit<U>(
+        nb, stride, cnt, i,
+        [&](int j) {
+          const double4 p = pos[j];
+          return AdjRec1{p.x, p.y, p.z, G[j], G[n + j], G[2 * n + j]};
+        },
+        [&](const AdjRec1& q) {
+          double d[3];
+          const double r2 = disp2(q.x, q.y, q.z, d);
+          if (!(r2 < rc2)) return;
+          const double ir = rsqrt_nr(r2);
+          const double u = (r2 * ir - g.r_lo) * g.r_inv_h;
+          umin = fmin(umin, u);
+          umax = fmax(umax, u);
+          double tt;
+          const int k = interval_u(u, g.nr, tt);
+          const double w = fma(gix - q.gx, d[0], fma(giy - q.gy, d[1], (giz - q.gz) * d[2])) * ir;
+          const double t2 = tt * tt, s = 1.0 - tt;
+          const double gb[4] = {-(s * s), tt * fma(3.0, tt, -4.0), fma(-3.0, t2, fma(2.0, tt, 1.0)),
+                                t2};
+          const double A = w * k_phi, B = w * k_rho;
+          double dr = 0.0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double gq = gg[q] * g.r_inv_h;
-        drho += g.c_rho[k + q] * gq;
-        atomicAdd(&b_phi[k + q], -0.5 * gq * s);
-        atomicAdd(&b_rho[k + q], -fp * gq * s);
-      }
-      tau += drho * s;
-    }
-    tau = md_group_sum<LANES>(tau);
-    nb = neigh + (size_t)i * LANES + l;
-    const double cf = -fpp * tau;
-    for (int m = l; m < nn; m += LANES, nb += stride) {
-      const int j = *nb;
-      const double4 pj = pos[j];
-      double d[3] = {pj.x - pi.x, pj.y - pi.y, pj.z - pi.z};
+          for (int q4 = 0; q4 < 4; ++q4) {
+            atomicAdd(&b_phi[k + q4], gb[q4] * A);
+            atomicAdd(&b_rho[k + q4], gb[q4] * B);
+            dr = fma(c_rho[k + q4], gb[q4], dr);
+          }
+          tau_w = fma(dr, w, tau_w);
+        });
+    oor = umin < 0.0 || umax > (double)g.nr;
+    // tau_i = sum_j rho'(r_ij) s_ij
+    const double tau = -0.5 * g.r_inv_h * md_group_sum<LANES>(tau_w);
+    const double cf = -fpp * tau * (1.0 / 6.0);
+    adj_visit<U>(
+        nb, stride, cnt, i,
+        [&](int j) {
+          const double4 p = pos[j];
+          return make_double3(p.x, p.y, p.z);
+        },
+        [&](const double3& q) {
+          double d[3];
+          const double r2 = disp2(q.x, q.y, q.z, d);
+          if (!(r2 < rc2)) return;
+          double tt;
+          const int k = interval_u((r2 * rsqrt_nr(r2) - g.r_lo) * g.r_inv_h, g.nr, tt);
+          const double t2 = tt * tt, s = 1.0 - tt;
+          const double bb[4] = {s * s * s, fma(t2, fma(3.0, tt, -6.0), 4.0),
+                                fma(tt, fma(tt, fma(-3.0, tt, 3.0), 3.0), 1.0), t2 * tt};
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        if (per[q]) d[q] -= len[q] * rint(d[q] * inv[q]);
-      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      if (!(r2 < rc2)) continue;
-      double tt, bb[4], gg[4];
-      const int k = interval(sqrt(r2), g.r_lo, g.r_inv_h, g.nr, tt, oor);
-      bspline_basis(tt, bb, gg);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) atomicAdd(&b_rho[k + q], cf * bb[q]);
-    }
+          for (int q4 = 0; q4 < 4; ++q4) atomicAdd(&b_rho[k + q4], cf * bb[q4]);
+        });
     if (l == 0) {
       double tt, bb[4], gg[4];
       const int k = interval(saved[i], g.e_lo, g.e_inv_h, g.ne, tt, oor);
@@ -141,21 +226,26 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_adjoint(
     if ((threadIdx.x & (MD_WAVE - 1)) == 0) md_flag(ctl, MD_FLAG_TABLE_RANGE);
   }
   __syncthreads();
-  double* out = tile_bins + (size_t)t * g.n_bins;
   for (int q = threadIdx.x; q < g.n_bins; q += blockDim.x) {
-    double s = bins[q];
-    for (int w = 1; w < nw; ++w) s += bins[(size_t)w * g.n_bins + q];
-    out[q] = s;
+    double s = 0.0;
+    if (q < n_hot) {
+      for (int c = 0; c < n_copy; ++c) s += bins[(size_t)c * g.stride + q];
+    } else {
+      for (int w = 0; w < nw; ++w) s += emb_bins[(size_t)w * g.n_emb + q - n_hot];
+    }
+    tile_bins[(size_t)q * b.n_tiles + t] = s;
   }
 }
 
-// grad[q] = sum over tiles of tile_bins[tile][q], in tile order (one block per bin).
+// grad[q] = sum over tiles of the tile partials tile_bins[q][tile] (bin-major, so one
+// block reads one contiguous row): thread h adds tiles h, h + 256, ... in order and
+// the block's threads are combined in a fixed tree.
 __global__ __launch_bounds__(256) void k_adj_reduce(const double* tile_bins, int n_tiles,
                                                     int n_bins, double* grad) {
   __shared__ double sh[4];
   const int q = blockIdx.x;
   double v[1] = {0.0};
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) v[0] += tile_bins[(size_t)t * n_bins + q];
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) v[0] += tile_bins[(size_t)q * n_tiles + t];
   md_block_sum<1>(v, sh);
   if (threadIdx.x == 0) grad[q] = v[0];
 }
@@ -206,12 +296,19 @@ extern "C" int md_eam_backward(const md_batch* b, const md_eam* p, md_precision 
   const int npad = md_npad(b->n_atoms);
   if (b->n_tiles > 0) {
     const dim3 grid(md_grid_blocks(b->n_tiles)), block(64 * L);
-    const size_t lds = (size_t)(64 * L / MD_WAVE) * g.n_bins * sizeof(double);
+    const int nw = 64 * L / MD_WAVE, n_hot = g.n_phi + g.n_rho;
+    g.stride = n_hot + (36 - n_hot % 32) % 32;  // copies start 8 banks apart
+    auto lds_of = [&](int c) {
+      return ((size_t)nw * ((size_t)c * g.stride + g.n_emb) + g.n_rho) * sizeof(double);
+    };
+    g.copies = MD_ADJ_COPIES;
+    while (g.copies > 1 && lds_of(g.copies) > MD_ADJ_LDS) g.copies >>= 1;
+    const size_t lds = lds_of(g.copies);
     if (lds > 65536) return MD_ERR_ARG;  // fewer lanes per atom, or fewer coefficients
-#define MD_ADJ_LAUNCH(LN)                                                                      \
-  MD_LAUNCH_TIMED(MD_KERNEL_EAM_ADJOINT, k_eam_adjoint<LN>, grid, block, lds, st, *b,          \
-                  (const double4*)pos, nl->neigh, nl->nneigh, npad, saved, grad_force, g, rc2, \
-                  tile_bins, (md_ctl_dev*)ctl)
+#define MD_ADJ_LAUNCH(LN)                                                                    \
+  MD_LAUNCH_TIMED(MD_KERNEL_EAM_ADJOINT, (k_eam_adjoint<LN, MD_ADJ_U>), grid, block, lds, st, \
+                  *b, (const double4*)pos, nl->neigh, nl->nneigh, npad, saved, grad_force, g,  \
+                  rc2, tile_bins, (md_ctl_dev*)ctl)
     switch (L) {
       case 1: MD_ADJ_LAUNCH(1); break;
       case 2: MD_ADJ_LAUNCH(2); break;
