@@ -30,7 +30,8 @@
  *   - A batch may hold no atoms (n_atoms = 0, n_tiles = 0, tiles may then be
  *     NULL; a box of a batch may be empty too).  With n_atoms = 0 every entry
  *     point checks its arguments and returns MD_OK without enqueuing work, except
- *     md_profiles and md_eam_backward, which still write their (zero) results.
+ *     md_profiles, md_eam_backward and md_force_loss, which still write their
+ *     (zero) results.
  *   - Return values are md_status codes.  Argument errors return at once and
  *     enqueue nothing.  Conditions detected on the device set sticky bits in
  *     the control block; md_read_flags() reads and maps them.
@@ -396,6 +397,18 @@ int md_verlet_step(const md_batch* b, md_verlet_phase phase, double dt, double* 
                    double* vel, const void* force, md_precision prec, double inv_mass,
                    const md_walls* walls, const md_langevin* lang, const double* pos_ref,
                    double half_skin, void* ctl, void* stream);
+
+/* Force-matching loss (the mean squared force error over all atoms of all boxes)
+ * and its cotangent: L = (1/n) sum_i |F_i - F_ref,i|^2 and G = dL/dF = (2/n)(F - F_ref),
+ * the G that md_eam_backward takes.  force: [3][n] as md_eam_forces writes it (float for
+ * MD_FP32, double for MD_FP64); f_ref: [3][n] FP64 in the same atom order; loss: one
+ * device double; grad_force: [3][n] FP64 or NULL (loss only); ws:
+ * md_force_loss_workspace_bytes(n) bytes.  FP64 sums in a fixed order that depends on n
+ * alone (bitwise reproducible).  n = 0 writes loss = 0.  MD_ERR_ARG for n < 0 or a NULL
+ * loss, ws, force or f_ref (the last two only for n > 0). */
+size_t md_force_loss_workspace_bytes(int n_atoms);
+int md_force_loss(int n_atoms, md_precision prec, const void* force, const double* f_ref,
+                  double* loss, double* grad_force, void* ws, void* stream);
 
 /* Derivative of a loss of the EAM forces of md_eam_forces (Sec. 1.6, eq. 1.6) with
  * respect to the potential's tables -- the hand-written counterpart of the automatic

@@ -78,6 +78,17 @@ def cotangents(snaps, c, grids, f_ref):
     return [2.0 * (forces(s, c, grids)[0] - fr) / natoms for s, fr in zip(snaps, f_ref)]
 
 
+def force_loss(F, f_ref):
+    """Loss and cotangents of given per-snapshot forces F (lists of [N_s, 3] arrays):
+    L = 1/(S N) sum_s sum_i |F_i - F_ref,i|^2 and G_i = 2 (F_i - F_ref,i) / (S N)."""
+    natoms = sum(len(f) for f in F)
+    tot = 0.0
+    for f, fr in zip(F, f_ref):
+        tot += float(np.sum((np.asarray(f, np.float64) - fr) ** 2))
+    G = [2.0 * (np.asarray(f, np.float64) - fr) / natoms for f, fr in zip(F, f_ref)]
+    return tot / natoms, G
+
+
 def vjp(snaps, c, grids, G):
     """sum_s sum_i G_i . dF_i/dc for arbitrary cotangents G; returns (g_phi, g_rho, g_F)."""
     c_phi, c_rho, c_emb = c

@@ -136,6 +136,8 @@ _SIGS = {
     "md_eam_backward": (_i, [_P(Batch), _P(EAM), _i, _vp, _P(NList), _vp, _vp, _vp, _vp, _vp,
                              _vp]),
     "md_backward_workspace_bytes": (_sz, [_P(Batch), _P(EAM)]),
+    "md_force_loss_workspace_bytes": (_sz, [_i]),
+    "md_force_loss": (_i, [_i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
     "md_atom_observables": (_i, [_P(Batch), _P(EAM), _P(LJ), _vp, _P(NList), _vp, _vp, _vp,
                                  _vp, _vp]),
     "md_profile_workspace_bytes": (_sz, [_i]),

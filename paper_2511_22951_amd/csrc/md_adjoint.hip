@@ -250,6 +250,45 @@ __global__ __launch_bounds__(256) void k_adj_reduce(const double* tile_bins, int
   if (threadIdx.x == 0) grad[q] = v[0];
 }
 
+// Force-matching loss and its cotangent: thread h of the fixed grid takes atoms
+// h, h + G, h + 2G, ... (G threads in all) in order; blocks are combined by
+// k_loss_final in block order, so the sum depends on n alone.
+constexpr int MD_LOSS_BLOCK = 256, MD_LOSS_MAX_BLOCKS = 1024;
+
+static inline int loss_blocks(int n) {
+  const int g = (n + MD_LOSS_BLOCK - 1) / MD_LOSS_BLOCK;
+  return g < MD_LOSS_MAX_BLOCKS ? (g > 0 ? g : 1) : MD_LOSS_MAX_BLOCKS;
+}
+
+template <typename R>
+__global__ __launch_bounds__(MD_LOSS_BLOCK) void k_loss_partial(int n, const R* __restrict__ F,
+                                                                const double* __restrict__ Fr,
+                                                                double two_over_n, double* G,
+                                                                double* part) {
+  __shared__ double sh[MD_LOSS_BLOCK / MD_WAVE];
+  double v[1] = {0.0};
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double d = (double)F[(size_t)c * n + i] - Fr[(size_t)c * n + i];
+      v[0] = fma(d, d, v[0]);
+      if (G) G[(size_t)c * n + i] = two_over_n * d;
+    }
+  }
+  md_block_sum<1>(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(MD_LOSS_BLOCK) void k_loss_final(int nb, const double* part,
+                                                              double inv_n, double* loss) {
+  __shared__ double sh[MD_LOSS_BLOCK / MD_WAVE];
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += part[b];
+  md_block_sum<1>(v, sh);
+  if (threadIdx.x == 0) *loss = v[0] * inv_n;
+}
+
 bool adj_ok(const md_eam* p) {
   if (!p || !p->phi.coef || !p->rho.coef || !p->emb.coef) return false;
   if (p->phi.ncoef < 6 || p->rho.ncoef < 6 || p->emb.ncoef < 6) return false;
@@ -321,6 +360,34 @@ extern "C" int md_eam_backward(const md_batch* b, const md_eam* p, md_precision 
   }
   hipLaunchKernelGGL(k_adj_reduce, dim3(g.n_bins), dim3(256), 0, st, tile_bins, b->n_tiles,
                      g.n_bins, grad_coef);
+  MD_LAUNCH_CHECK();
+  return MD_OK;
+}
+
+extern "C" size_t md_force_loss_workspace_bytes(int n_atoms) {
+  return n_atoms < 0 ? 0 : md_align256(sizeof(double) * (size_t)loss_blocks(n_atoms));
+}
+
+extern "C" int md_force_loss(int n_atoms, md_precision prec, const void* force, const double* f_ref,
+                             double* loss, double* grad_force, void* ws, void* stream) {
+  if (n_atoms < 0 || !loss || !ws) return MD_ERR_ARG;
+  if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
+  if (n_atoms > 0 && (!force || !f_ref)) return MD_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  double* part = (double*)ws;
+  const int nb = loss_blocks(n_atoms);
+  if (n_atoms > 0) {
+    const double two_over_n = 2.0 / n_atoms;
+    if (prec == MD_FP64)
+      hipLaunchKernelGGL(k_loss_partial<double>, dim3(nb), dim3(MD_LOSS_BLOCK), 0, st, n_atoms,
+                         (const double*)force, f_ref, two_over_n, grad_force, part);
+    else
+      hipLaunchKernelGGL(k_loss_partial<float>, dim3(nb), dim3(MD_LOSS_BLOCK), 0, st, n_atoms,
+                         (const float*)force, f_ref, two_over_n, grad_force, part);
+    MD_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(MD_LOSS_BLOCK), 0, st, n_atoms > 0 ? nb : 0,
+                     part, n_atoms > 0 ? 1.0 / n_atoms : 0.0, loss);
   MD_LAUNCH_CHECK();
   return MD_OK;
 }

@@ -3,8 +3,10 @@
 A batch of fixed snapshots is binned and listed once; the forces of a trainable
 EAM (three uniform cubic B-splines) come from md_eam_forces, and the gradient of
 any loss of those forces with respect to the spline coefficients comes from the
-hand-written adjoint kernel md_eam_backward, wrapped in a torch.autograd.Function.
-Torch only evaluates the loss and holds memory.
+hand-written adjoint kernel md_eam_backward, wrapped in a torch.autograd.Function
+(EAMForces).  The force-matching loss itself and its cotangent come from the library
+too (md_force_loss, in ForceMatchingLoss); torch then only holds memory and applies
+the chain rule's upstream scalar.
 """
 from __future__ import annotations
 
@@ -35,6 +37,7 @@ class SnapshotBatch:
         self.precision = precision
         self.saved = torch.zeros((3, self.n), dtype=torch.float64, device=device)
         self.bws = None
+        self.lws = None  # md_force_loss workspace
         ids = self.state.id.long()
         # current (cell) order -> original order permutation, for the caller's references
         self.order_ids = ids
@@ -47,6 +50,16 @@ class SnapshotBatch:
     def forces(self, pot: md.EAMPotential, saved=True):
         md.md_eam_forces(self.state, pot, self.nl, saved=self.saved if saved else None)
         return self.state.force.double()
+
+    def loss(self, pot: md.EAMPotential, f_ref, saved, grad_force):
+        """Forces at pot's coefficients ({rhobar, F', F''} into saved), then the loss against
+        f_ref ([3, n] FP64) as a 0-dim device tensor and its cotangent into grad_force."""
+        md.md_eam_forces(self.state, pot, self.nl, saved=saved)
+        if self.lws is None:
+            nb = int(N.lib().md_force_loss_workspace_bytes(self.n))
+            self.lws = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.state.pos.device)
+        return md.md_force_loss(self.state.force, f_ref, self.precision, grad_force=grad_force,
+                                ws=self.lws)
 
     def backward(self, pot: md.EAMPotential, grad_force, saved=None):
         """Gradient with respect to pot's current coefficients; `saved` ({rhobar, F', F''} of
@@ -103,7 +116,44 @@ class EAMForces(torch.autograd.Function):
         return g.to(ctx.coef_dtype), None, None
 
 
+class ForceMatchingLoss(torch.autograd.Function):
+    """loss = ForceMatchingLoss.apply(coef, batch, potential, f_ref): forces of the
+    concatenated (phi | rho | F) coefficients (md_eam_forces), their mean squared error
+    against f_ref ([3, n] FP64, current order) and its cotangent G = dL/dF (md_force_loss);
+    backward is md_eam_backward of G.  Like EAMForces, each call keeps its own
+    coefficients, {rhobar, F', F''} and G for its backward."""
+
+    @staticmethod
+    def forward(ctx, coef, batch: SnapshotBatch, pot: md.EAMPotential, f_ref):
+        c = coef.detach().to(torch.float64).contiguous()
+        pot.set_coefficients(*_split(pot, c))
+        saved = torch.empty((3, batch.n), dtype=torch.float64, device=f_ref.device)
+        G = torch.empty((3, batch.n), dtype=torch.float64, device=f_ref.device)
+        loss = batch.loss(pot, f_ref, saved, G)
+        ctx.batch, ctx.pot = batch, pot
+        ctx.coef = c.clone()
+        ctx.saved, ctx.G = saved, G
+        ctx.version = pot.version
+        ctx.coef_dtype = coef.dtype
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        pot = ctx.pot
+        if pot.version == ctx.version:
+            g = ctx.batch.backward(pot, ctx.G, saved=ctx.saved)
+        else:
+            later, later_version = torch.cat([c.clone() for c in pot.coef]), pot.version
+            pot.set_coefficients(*_split(pot, ctx.coef))
+            try:
+                g = ctx.batch.backward(pot, ctx.G, saved=ctx.saved)
+            finally:
+                pot.set_coefficients(*_split(pot, later))
+                pot.version = later_version
+        return (g * grad_loss).to(ctx.coef_dtype), None, None, None
+
+
 def force_matching_loss(coef, batch, pot, f_ref):
-    """L = 1/(S N) sum |F - F_ref|^2 over all atoms of all snapshots."""
-    f = EAMForces.apply(coef, batch, pot)
-    return ((f - f_ref) ** 2).sum() / batch.n
+    """L = 1/(S N) sum |F - F_ref|^2 over all atoms of all snapshots (f_ref: [3, n], current
+    order), differentiable with respect to coef."""
+    return ForceMatchingLoss.apply(coef, batch, pot, f_ref.to(torch.float64).contiguous())

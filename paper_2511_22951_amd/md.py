@@ -446,6 +446,34 @@ def md_profiles(st: State, axis, lo, width, n_bins, mass, e_atom=None, w_atom=No
     return out
 
 
+def md_force_loss(force, f_ref, precision, grad_force=None, ws=None, stream=None):
+    """L = (1/n) sum |F - F_ref|^2 over the n atoms of force ([3, n], float for MD_FP32, double
+    for MD_FP64) and f_ref ([3, n] FP64); writes G = (2/n)(F - F_ref) into grad_force ([3, n]
+    FP64) when given.  Returns L as a 0-dim device tensor."""
+    L = N.lib()
+    _require_cuda(f_ref.device)
+    fdt = torch.float32 if precision == N.MD_FP32 else torch.float64
+    if f_ref.dtype != torch.float64 or f_ref.dim() != 2 or f_ref.shape[0] != 3 or \
+            not f_ref.is_contiguous():
+        raise ValueError("f_ref must be a contiguous [3, n] float64 tensor")
+    if force.dtype != fdt or force.shape != f_ref.shape or not force.is_contiguous() or \
+            force.device != f_ref.device:
+        raise ValueError("force must be a contiguous [3, n] %s tensor" % fdt)
+    if grad_force is not None and (grad_force.dtype != torch.float64 or
+                                   grad_force.shape != f_ref.shape or
+                                   not grad_force.is_contiguous() or
+                                   grad_force.device != f_ref.device):
+        raise ValueError("grad_force must be a contiguous [3, n] float64 tensor")
+    n = int(f_ref.shape[1])
+    nb = int(L.md_force_loss_workspace_bytes(n))
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=f_ref.device)
+    loss = torch.empty((), dtype=torch.float64, device=f_ref.device)
+    check(L.md_force_loss(n, int(precision), _ptr(force), _ptr(f_ref), _ptr(loss),
+                          _ptr(grad_force), _ptr(ws), _stream(stream)), "md_force_loss")
+    return loss
+
+
 def md_eam_backward(st: State, pot: EAMPotential, nl: NeighborList, saved, grad_force, ws=None,
                     stream=None):
     """grad_force: [3, n] FP64 cotangent in the current atom order.  Returns [n_coef total]."""
@@ -455,7 +483,7 @@ def md_eam_backward(st: State, pot: EAMPotential, nl: NeighborList, saved, grad_
         raise ValueError("backward not available for this spline size")
     if ws is None or ws.numel() < nb:
         ws = torch.zeros(nb, dtype=torch.uint8, device=st.pos.device)
-    out = torch.zeros(sum(c.shape[0] for c in pot.coef), dtype=torch.float64, device=st.pos.device)
+    out = torch.empty(sum(c.shape[0] for c in pot.coef), dtype=torch.float64, device=st.pos.device)
     check(L.md_eam_backward(C.byref(st.plan.c), C.byref(pot.c), st.precision, _ptr(st.pos),
                             C.byref(nl.c), _ptr(saved), _ptr(grad_force), _ptr(out), _ptr(ws),
                             _ptr(st.ctl), _stream(stream)), "md_eam_backward")

@@ -140,6 +140,55 @@ def _fm_problem(md, n_snap=3, cells=5, prec=0):
     return snaps, osnaps, grids, c_or, pot, batch
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", [0, 1, 1000, 300000])
+def test_force_loss_matches_oracle(md, prec, n):
+    """md_force_loss on seeded forces (one block, a ragged block and a grid that strides
+    over the atoms): the loss within 1e-14 relative of the oracle's, the cotangent within
+    1e-15 of its largest entry, both bitwise reproducible; n = 0 gives loss 0."""
+    rng = np.random.default_rng(500 + n)
+    F = rng.normal(size=(n, 3))
+    Fr = rng.normal(size=(n, 3))
+    if prec == 1:
+        F = F.astype(np.float32)
+    dt = torch.float32 if prec == 1 else torch.float64
+    force = torch.as_tensor(np.ascontiguousarray(F.T), dtype=dt, device="cuda")
+    f_ref = torch.as_tensor(np.ascontiguousarray(Fr.T), device="cuda")
+    G = torch.full((3, n), 7.0, dtype=torch.float64, device="cuda")
+    loss = md.md_force_loss(force, f_ref, prec, grad_force=G)
+    if n == 0:
+        assert loss.item() == 0.0
+        return
+    want_L, want_G = oadj.force_loss([F.astype(np.float64)], [Fr])
+    assert abs(loss.item() - want_L) <= 1e-14 * want_L
+    got_G = G.t().cpu().numpy()
+    assert np.max(np.abs(got_G - want_G[0])) <= 1e-15 * np.max(np.abs(want_G[0]))
+    G2 = torch.empty_like(G)
+    assert torch.equal(md.md_force_loss(force, f_ref, prec, grad_force=G2), loss)
+    assert torch.equal(G2, G)
+    assert torch.equal(md.md_force_loss(force, f_ref, prec), loss)  # loss only
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_loss_equals_force_path(md, prec):
+    """force_matching_loss (forces, loss and cotangent in the library) against EAMForces with
+    the loss written in torch: same loss to 1e-13 and same gradient to 1e-12, FP64 and FP32."""
+    from paper_2511_22951_amd import fm
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, n_snap=2, prec=prec)
+    ref_pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
+    f_ref = batch.forces(ref_pot, saved=False).clone()
+    c1 = torch.cat([c.clone() for c in pot.coef]).requires_grad_(True)
+    l1 = fm.force_matching_loss(c1, batch, pot, f_ref)
+    l1.backward()
+    c2 = torch.cat([c.clone() for c in pot.coef]).requires_grad_(True)
+    f = fm.EAMForces.apply(c2, batch, pot)
+    l2 = ((f - f_ref) ** 2).sum() / batch.n
+    l2.backward()
+    assert abs(l1.item() - l2.item()) <= 1e-13 * l2.item()
+    g1, g2 = c1.grad.cpu().numpy(), c2.grad.cpu().numpy()
+    assert np.max(np.abs(g1 - g2)) <= 1e-12 * np.max(np.abs(g2))
+
+
 def test_adjoint_vjp_matches_oracle(md):
     snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md)
     G = [mi.random_cotangent(len(s.pos), seed=40 + k) for k, s in enumerate(snaps)]

@@ -82,3 +82,43 @@ def test_loss_quadratic_in_phi_block(problem):
 def test_unperturbed_spline_is_close_to_reference(problem):
     snaps, snaps_in, c, c0, grids, f_ref = problem
     assert adj.loss(snaps, c0, grids, f_ref) < 1e-4 * adj.loss(snaps, c, grids, f_ref)
+
+
+def test_force_loss_pins():
+    """force_loss on given forces: zero at F = F_ref; a uniform offset d on every component of
+    every atom gives L = 3 d^2 whatever the snapshot sizes; G is the central difference of L in
+    each force component (catches the factor 2 and the 1/(S N) normalisation); brute force
+    over atoms and components on a tiny input."""
+    rng = np.random.default_rng(11)
+    f_ref = [rng.normal(size=(5, 3)), rng.normal(size=(2, 3))]
+    L0, G0 = adj.force_loss([f.copy() for f in f_ref], f_ref)
+    assert L0 == 0.0 and all(np.all(g == 0.0) for g in G0)
+    L1, _ = adj.force_loss([f + 0.25 for f in f_ref], f_ref)
+    assert abs(L1 - 3 * 0.25 ** 2) < 1e-15
+    F = [f + rng.normal(scale=0.3, size=f.shape) for f in f_ref]
+    L, G = adj.force_loss(F, f_ref)
+    brute = 0.0
+    for f, fr in zip(F, f_ref):
+        for i in range(len(f)):
+            for a in range(3):
+                brute += (f[i, a] - fr[i, a]) * (f[i, a] - fr[i, a])
+    assert abs(L - brute / 7) < 1e-14
+    h = 1e-6
+    for s in range(2):
+        for i in range(len(F[s])):
+            for a in range(3):
+                Fp = [f.copy() for f in F]
+                Fm = [f.copy() for f in F]
+                Fp[s][i, a] += h
+                Fm[s][i, a] -= h
+                fd = (adj.force_loss(Fp, f_ref)[0] - adj.force_loss(Fm, f_ref)[0]) / (2 * h)
+                assert abs(fd - G[s][i, a]) < 1e-8
+
+
+def test_force_loss_agrees_with_loss_and_cotangents(problem):
+    snaps, snaps_in, c, c0, grids, f_ref = problem
+    F = [adj.forces(s, c, grids)[0] for s in snaps]
+    L, G = adj.force_loss(F, f_ref)
+    assert abs(L - adj.loss(snaps, c, grids, f_ref)) <= 1e-15 * L
+    for g, g2 in zip(G, adj.cotangents(snaps, c, grids, f_ref)):
+        assert np.array_equal(g, g2)
