@@ -121,7 +121,7 @@ def test_batched_graph_replay_equals_eager(md):
 # ----------------------------------------------------------------------------
 # adjoint
 # ----------------------------------------------------------------------------
-def _fm_problem(md, n_snap=3, cells=5, prec=0):
+def _fm_problem(md, n_snap=3, cells=5, prec=0, lanes=4):
     from paper_2511_22951_amd import fm
     tab = mi.force_matching_tables()
     noise = mi.coefficient_noise()
@@ -136,7 +136,7 @@ def _fm_problem(md, n_snap=3, cells=5, prec=0):
     nz = torch.as_tensor(noise, device="cuda")
     pot = md.EAMPotential(fits[0] * nz[:64], fits[1] * nz[64:128], fits[2] * nz[128:],
                           tab.rho.x_lo, tab.rho.h, tab.emb.x_lo, tab.emb.h, mi.EAM_CU.r_cut)
-    batch = fm.SnapshotBatch(snaps, mi.EAM_CU.r_cut + 0.3, precision=prec)
+    batch = fm.SnapshotBatch(snaps, mi.EAM_CU.r_cut + 0.3, precision=prec, lanes=lanes)
     return snaps, osnaps, grids, c_or, pot, batch
 
 
@@ -199,6 +199,20 @@ def test_adjoint_vjp_matches_oracle(md):
     assert np.max(np.abs(got - want)) < 1e-10 * np.max(np.abs(want))
     got2 = batch.backward(pot, batch.to_current_order(np.concatenate(G))).cpu().numpy()
     assert np.array_equal(got, got2)  # run-to-run bitwise reproducible
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 8, 16])
+def test_adjoint_vjp_every_lane_count(md, lanes):
+    """The adjoint at every lane count the list allows (a different number of bin copies
+    per wavefront fits the LDS at each: 8, 8, 4, 2; 16 lanes leave about five list entries
+    per lane) against the oracle's chain-rule VJP, 1e-10 relative."""
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, n_snap=2, lanes=lanes)
+    G = [mi.random_cotangent(len(s.pos), seed=60 + k) for k, s in enumerate(snaps)]
+    want = np.concatenate(oadj.vjp(osnaps, c_or, grids, G))
+    batch.forces(pot, saved=True)
+    got = batch.backward(pot, batch.to_current_order(np.concatenate(G))).cpu().numpy()
+    batch.state.check_flags()
+    assert np.max(np.abs(got - want)) < 1e-10 * np.max(np.abs(want))
 
 
 def test_force_matching_gradient_matches_oracle_and_fd(md):
