@@ -30,8 +30,8 @@
  *   - A batch may hold no atoms (n_atoms = 0, n_tiles = 0, tiles may then be
  *     NULL; a box of a batch may be empty too).  With n_atoms = 0 every entry
  *     point checks its arguments and returns MD_OK without enqueuing work, except
- *     md_profiles, md_eam_backward and md_force_loss, which still write their
- *     (zero) results.
+ *     md_profiles, md_eam_backward, md_eam_backward_jac and md_force_loss, which still
+ *     write their (zero) results.
  *   - Return values are md_status codes.  Argument errors return at once and
  *     enqueue nothing.  Conditions detected on the device set sticky bits in
  *     the control block; md_read_flags() reads and maps them.
@@ -398,6 +398,16 @@ int md_verlet_step(const md_batch* b, md_verlet_phase phase, double dt, double* 
                    const md_walls* walls, const md_langevin* lang, const double* pos_ref,
                    double half_skin, void* ctl, void* stream);
 
+/* Density Jacobian of fixed positions for the EAM of Sec. 1.6: jac[i][k] = d rhobar_i /
+ * d c_rho_k = sum_j beta_k(r_ij) over the pairs of atom i within r_cut (rhobar is linear
+ * in the density coefficients, so jac depends on the positions, the list, the rho grid and
+ * r_cut, not on coefficient values).  jac: [n][rho.ncoef] FP64, row-major, current atom
+ * order, md_density_jacobian_bytes(b, p) bytes, overwritten.  rho.ncoef at most 128
+ * (bytes 0 and MD_ERR_ARG otherwise).  Deterministic.  Table-range flag as the forces. */
+size_t md_density_jacobian_bytes(const md_batch* b, const md_eam* p);
+int md_eam_density_jacobian(const md_batch* b, const md_eam* p, const double* pos,
+                            const md_nlist* nl, double* jac, void* ctl, void* stream);
+
 /* Force-matching loss (the mean squared force error over all atoms of all boxes)
  * and its cotangent: L = (1/n) sum_i |F_i - F_ref,i|^2 and G = dL/dF = (2/n)(F - F_ref),
  * the G that md_eam_backward takes.  force: [3][n] as md_eam_forces writes it (float for
@@ -424,6 +434,15 @@ size_t md_backward_workspace_bytes(const md_batch* b, const md_eam* p);
 int md_eam_backward(const md_batch* b, const md_eam* p, md_precision prec, const double* pos,
                     const md_nlist* nl, const double* saved, const double* grad_force,
                     double* grad_coef, void* ws, void* ctl, void* stream);
+/* md_eam_backward for fixed positions whose density Jacobian `jac` (from
+ * md_eam_density_jacobian, same positions, list and rho grid) is kept: the F'' term of
+ * the rho gradient, sum_i F''_i tau_i jac[i][k], is taken from jac instead of a second
+ * visit of every list.  Same arguments, workspace and result (to rounding) otherwise;
+ * deterministic.  MD_ERR_ARG for a NULL jac. */
+int md_eam_backward_jac(const md_batch* b, const md_eam* p, md_precision prec,
+                        const double* pos, const md_nlist* nl, const double* saved,
+                        const double* jac, const double* grad_force, double* grad_coef,
+                        void* ws, void* ctl, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Behler-Parrinello network potential (Sec. 2.1)

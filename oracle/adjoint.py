@@ -89,6 +89,15 @@ def force_loss(F, f_ref):
     return tot / natoms, G
 
 
+def density_jacobian(snap: Snapshot, g_rho):
+    """R [n, ncoef]: R_ak = d rhobar_a / d c_rho_k = sum over the pairs (a, j) of beta_k(r_aj)
+    (rhobar is linear in the density coefficients)."""
+    idx, W0 = sp.basis_weights(g_rho.ncoef, g_rho.x_lo, g_rho.h, snap.r, 0)
+    R = np.zeros((snap.n, g_rho.ncoef))
+    np.add.at(R, (np.repeat(snap.i, 4), idx.ravel()), W0.ravel())
+    return R
+
+
 def vjp(snaps, c, grids, G):
     """sum_s sum_i G_i . dF_i/dc for arbitrary cotangents G; returns (g_phi, g_rho, g_F)."""
     c_phi, c_rho, c_emb = c
@@ -112,10 +121,8 @@ def vjp(snaps, c, grids, G):
         # density block, direct term
         idx, W = sp.basis_weights(g_rho.ncoef, g_rho.x_lo, g_rho.h, snap.r, 1)
         np.add.at(out_rho, idx, -W * ((fp[snap.i] + fp[snap.j]) * g)[:, None])
-        # density block, through rhobar: R_ak = d rhobar_a / d c_rho_k
-        idx, W0 = sp.basis_weights(g_rho.ncoef, g_rho.x_lo, g_rho.h, snap.r, 0)
-        R = np.zeros((snap.n, g_rho.ncoef))
-        np.add.at(R, (np.repeat(snap.i, 4), idx.ravel()), W0.ravel())
+        # density block, through rhobar
+        R = density_jacobian(snap, g_rho)
         coef_i = fpp[snap.i] * q
         coef_j = fpp[snap.j] * q
         out_rho -= coef_i @ R[snap.i] + coef_j @ R[snap.j]

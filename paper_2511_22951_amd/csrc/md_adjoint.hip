@@ -29,6 +29,7 @@ namespace {
 #define MD_ADJ_U 2        // list entries in flight per lane
 #define MD_ADJ_COPIES 8   // most copies of the phi and rho bins per wavefront
 #define MD_ADJ_LDS 49152  // LDS per block that the copies may fill
+#define MD_JAC_MAX_COEF 128  // density Jacobian: rows of 64 atoms in LDS (64 KiB)
 
 __device__ __forceinline__ void bspline_basis(double t, double b[4], double g[4]) {
   const double s = 1.0 - t;
@@ -110,20 +111,50 @@ struct AdjRec1 {
   double x, y, z, gx, gy, gz;
 };
 
+// Minimum-image separation d = x_j - x_i (a non-periodic axis has inv = 0, so its
+// shift is 0) and its square, with the multiply-adds written out so that every
+// kernel decides r < r_c on the same bits.
+__device__ __forceinline__ double pair_disp2(const double4& pi, double x, double y, double z,
+                                             const double len[3], const double inv[3],
+                                             double d[3]) {
+  d[0] = x - pi.x;
+  d[1] = y - pi.y;
+  d[2] = z - pi.z;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) d[q] = fma(-len[q], rint(d[q] * inv[q]), d[q]);
+  return fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+}
+
+// 6 beta_{k+q}(t), q = 0..3, of the cubic B-spline on the interval's local t.
+__device__ __forceinline__ void basis6(double tt, double bb[4]) {
+  const double t2 = tt * tt, s = 1.0 - tt;
+  bb[0] = s * s * s;
+  bb[1] = fma(t2, fma(3.0, tt, -6.0), 4.0);
+  bb[2] = fma(tt, fma(tt, fma(-3.0, tt, 3.0), 3.0), 1.0);
+  bb[3] = t2 * tt;
+}
+
 // Per pair the basis enters through fixed multiples that are taken out of the
 // loops: 2 beta'_k(t) / h (the factor 1/2 and 1/h go into the per-atom weights) in
 // the first visit and 6 beta_k(t) (the 1/6 goes into c_F'') in the second.
-template <int LANES, int U>
+// JAC: the second visit is replaced by the density Jacobian of the atoms
+// (jac[i][k] = d rhobar_i / d c_rho_k, fixed positions): its F'' term,
+// sum_i F''_i tau_i jac[i][k], is one product of the tile's rows with the weights
+// -F''_i tau_i, wave w taking atoms w, w + waves, ... in order.
+template <int LANES, int U, bool JAC>
 __global__ __launch_bounds__(64 * LANES) void k_eam_adjoint(
     md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
     const int* __restrict__ nneigh, int npad, const double* __restrict__ saved,
-    const double* __restrict__ G, AdjGeom g, double rc2, double* tile_bins, md_ctl_dev* ctl) {
-  // LDS: phi|rho bins [waves][copies][stride], F bins [waves][n_emb], rho coefficients
+    const double* __restrict__ jac, const double* __restrict__ G, AdjGeom g, double rc2,
+    double* tile_bins, md_ctl_dev* ctl) {
+  // LDS: phi|rho bins [waves][copies][stride], F bins [waves][n_emb], rho coefficients,
+  // and (JAC) the tile's per-atom weights
   extern __shared__ double bins[];
   const int nw = blockDim.x / MD_WAVE, wid = threadIdx.x / MD_WAVE;
   const int n_hot = g.n_phi + g.n_rho, n_copy = nw * g.copies;
   double* emb_bins = bins + (size_t)n_copy * g.stride;
   double* c_rho = emb_bins + (size_t)nw * g.n_emb;
+  double* s_w = c_rho + g.n_rho;  // [64] (JAC)
   for (int q = threadIdx.x; q < n_copy * g.stride + nw * g.n_emb; q += blockDim.x) bins[q] = 0.0;
   for (int q = threadIdx.x; q < g.n_rho; q += blockDim.x) c_rho[q] = g.c_rho[q];
   __syncthreads();
@@ -152,12 +183,7 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_adjoint(
     const size_t stride = (size_t)npad * LANES;
     const int* nb = neigh + (size_t)i * LANES + l;
     auto disp2 = [&](double x, double y, double z, double d[3]) {
-      d[0] = x - pi.x;
-      d[1] = y - pi.y;
-      d[2] = z - pi.z;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) d[q] = fma(-len[q], rint(d[q] * inv[q]), d[q]);
-      return fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+      return pair_disp2(pi, x, y, z, len, inv, d);
     };
     // first visit: w_ij = (G_i - G_j) . (r_j - r_i) / r_ij = -s_ij
     const double k_phi = 0.25 * g.r_inv_h, k_rho = 0.5 * g.r_inv_h * fp;
@@ -195,25 +221,27 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_adjoint(
     oor = umin < 0.0 || umax > (double)g.nr;
     // tau_i = sum_j rho'(r_ij) s_ij
     const double tau = -0.5 * g.r_inv_h * md_group_sum<LANES>(tau_w);
-    const double cf = -fpp * tau * (1.0 / 6.0);
-    adj_visit<U>(
-        nb, stride, cnt, i,
-        [&](int j) {
-          const double4 p = pos[j];
-          return make_double3(p.x, p.y, p.z);
-        },
-        [&](const double3& q) {
-          double d[3];
-          const double r2 = disp2(q.x, q.y, q.z, d);
-          if (!(r2 < rc2)) return;
-          double tt;
-          const int k = interval_u((r2 * rsqrt_nr(r2) - g.r_lo) * g.r_inv_h, g.nr, tt);
-          const double t2 = tt * tt, s = 1.0 - tt;
-          const double bb[4] = {s * s * s, fma(t2, fma(3.0, tt, -6.0), 4.0),
-                                fma(tt, fma(tt, fma(-3.0, tt, 3.0), 3.0), 1.0), t2 * tt};
+    if (JAC) {
+      if (l == 0) s_w[a] = -fpp * tau;
+    } else {
+      const double cf = -fpp * tau * (1.0 / 6.0);
+      adj_visit<U>(
+          nb, stride, cnt, i,
+          [&](int j) {
+            const double4 p = pos[j];
+            return make_double3(p.x, p.y, p.z);
+          },
+          [&](const double3& q) {
+            double d[3];
+            const double r2 = disp2(q.x, q.y, q.z, d);
+            if (!(r2 < rc2)) return;
+            double tt, bb[4];
+            const int k = interval_u((r2 * rsqrt_nr(r2) - g.r_lo) * g.r_inv_h, g.nr, tt);
+            basis6(tt, bb);
 #pragma unroll
-          for (int q4 = 0; q4 < 4; ++q4) atomicAdd(&b_rho[k + q4], cf * bb[q4]);
-        });
+            for (int q4 = 0; q4 < 4; ++q4) atomicAdd(&b_rho[k + q4], cf * bb[q4]);
+          });
+    }
     if (l == 0) {
       double tt, bb[4], gg[4];
       const int k = interval(saved[i], g.e_lo, g.e_inv_h, g.ne, tt, oor);
@@ -224,6 +252,18 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_adjoint(
   }
   if (__any(oor)) {
     if ((threadIdx.x & (MD_WAVE - 1)) == 0) md_flag(ctl, MD_FLAG_TABLE_RANGE);
+  }
+  if (JAC) {
+    __syncthreads();
+    // into copy 0 of this wave's rho bins: lane k owns bin k, after the wave's own adds
+    double* rho0 = bins + (size_t)wid * g.copies * g.stride + g.n_phi;
+    const int lane = threadIdx.x & (MD_WAVE - 1);
+    for (int k = lane; k < g.n_rho; k += MD_WAVE) {
+      double acc = 0.0;
+      for (int a2 = wid; a2 < T.count; a2 += nw)
+        acc = fma(s_w[a2], jac[(size_t)(T.first + a2) * g.n_rho + k], acc);
+      rho0[k] += acc;
+    }
   }
   __syncthreads();
   for (int q = threadIdx.x; q < g.n_bins; q += blockDim.x) {
@@ -248,6 +288,63 @@ __global__ __launch_bounds__(256) void k_adj_reduce(const double* tile_bins, int
   for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) v[0] += tile_bins[(size_t)q * n_tiles + t];
   md_block_sum<1>(v, sh);
   if (threadIdx.x == 0) grad[q] = v[0];
+}
+
+// Density Jacobian of fixed positions: jac[i][k] = d rhobar_i / d c_rho_k =
+// sum_j beta_k(r_ij) over i's pairs within r_c.  Each atom of the tile owns an LDS
+// row; its lanes add 6 beta in list order, and the row is scaled by 1/6 on the way out.
+template <int LANES, int U>
+__global__ __launch_bounds__(64 * LANES) void k_density_jacobian(
+    md_batch b, const double4* __restrict__ pos, const int* __restrict__ neigh,
+    const int* __restrict__ nneigh, int npad, AdjGeom g, double rc2, double* jac,
+    md_ctl_dev* ctl) {
+  extern __shared__ double rows[];  // [64][n_rho]
+  for (int q = threadIdx.x; q < MD_TILE * g.n_rho; q += blockDim.x) rows[q] = 0.0;
+  __syncthreads();
+  const int t = md_remap_block(b.n_tiles);
+  if (t >= b.n_tiles) return;
+  const md_tile T = b.tiles[t];
+  const md_domain& Dm = b.domains[T.rep];
+  const double len[3] = {Dm.len[0], Dm.len[1], Dm.len[2]};
+  const double inv[3] = {Dm.periodic[0] ? Dm.inv_len[0] : 0.0,
+                         Dm.periodic[1] ? Dm.inv_len[1] : 0.0,
+                         Dm.periodic[2] ? Dm.inv_len[2] : 0.0};
+  const int a = threadIdx.x / LANES, l = threadIdx.x % LANES;
+  bool oor = false;
+  if (a < T.count) {
+    const int i = T.first + a;
+    const double4 pi = pos[i];
+    const int nn = nneigh[i] & MD_NN_MASK;
+    const int cnt = nn > l ? (nn - l + LANES - 1) / LANES : 0;
+    double* row = rows + (size_t)a * g.n_rho;
+    double umin = 0.0, umax = 0.0;
+    adj_visit<U>(
+        neigh + (size_t)i * LANES + l, (size_t)npad * LANES, cnt, i,
+        [&](int j) {
+          const double4 p = pos[j];
+          return make_double3(p.x, p.y, p.z);
+        },
+        [&](const double3& q) {
+          double d[3];
+          const double r2 = pair_disp2(pi, q.x, q.y, q.z, len, inv, d);
+          if (!(r2 < rc2)) return;
+          const double u = (r2 * rsqrt_nr(r2) - g.r_lo) * g.r_inv_h;
+          umin = fmin(umin, u);
+          umax = fmax(umax, u);
+          double tt, bb[4];
+          const int k = interval_u(u, g.nr, tt);
+          basis6(tt, bb);
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4) atomicAdd(&row[k + q4], bb[q4]);
+        });
+    oor = umin < 0.0 || umax > (double)g.nr;
+  }
+  if (__any(oor)) {
+    if ((threadIdx.x & (MD_WAVE - 1)) == 0) md_flag(ctl, MD_FLAG_TABLE_RANGE);
+  }
+  __syncthreads();
+  double* out = jac + (size_t)T.first * g.n_rho;
+  for (int q = threadIdx.x; q < T.count * g.n_rho; q += blockDim.x) out[q] = rows[q] * (1.0 / 6.0);
 }
 
 // Force-matching loss and its cotangent: thread h of the fixed grid takes atoms
@@ -306,17 +403,9 @@ extern "C" size_t md_backward_workspace_bytes(const md_batch* b, const md_eam* p
   return md_align256(8 * nb * (size_t)(b->n_tiles > 0 ? b->n_tiles : 1));
 }
 
-extern "C" int md_eam_backward(const md_batch* b, const md_eam* p, md_precision prec,
-                               const double* pos, const md_nlist* nl, const double* saved,
-                               const double* grad_force, double* grad_coef, void* ws, void* ctl,
-                               void* stream) {
-  if (!md_batch_ok(b)) return MD_ERR_ARG;
-  if (!adj_ok(p) || !pos || !nl || !nl->neigh || !nl->nneigh || !saved || !grad_force ||
-      !grad_coef || !ws || !ctl)
-    return MD_ERR_ARG;
-  if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
-  const int L = nl->lanes;
-  if ((L != 1 && L != 2 && L != 4 && L != 8 && L != 16) || nl->max_neigh % L) return MD_ERR_ARG;
+namespace {
+
+AdjGeom adj_geom(const md_eam* p) {
   AdjGeom g;
   g.c_rho = p->rho.coef;
   g.r_lo = p->rho.x_lo;
@@ -329,6 +418,27 @@ extern "C" int md_eam_backward(const md_batch* b, const md_eam* p, md_precision 
   g.n_rho = p->rho.ncoef;
   g.n_emb = p->emb.ncoef;
   g.n_bins = g.n_phi + g.n_rho + g.n_emb;
+  g.copies = 1;
+  g.stride = g.n_phi + g.n_rho;
+  return g;
+}
+
+bool lanes_ok(const md_nlist* nl) {
+  const int L = nl->lanes;
+  return (L == 1 || L == 2 || L == 4 || L == 8 || L == 16) && nl->max_neigh % L == 0;
+}
+
+int backward(const md_batch* b, const md_eam* p, md_precision prec, const double* pos,
+             const md_nlist* nl, const double* saved, const double* jac,
+             const double* grad_force, double* grad_coef, void* ws, void* ctl, void* stream) {
+  if (!md_batch_ok(b)) return MD_ERR_ARG;
+  if (!adj_ok(p) || !pos || !nl || !nl->neigh || !nl->nneigh || !saved || !grad_force ||
+      !grad_coef || !ws || !ctl)
+    return MD_ERR_ARG;
+  if (prec != MD_FP64 && prec != MD_FP32) return MD_ERR_ARG;
+  if (!lanes_ok(nl)) return MD_ERR_ARG;
+  const int L = nl->lanes;
+  AdjGeom g = adj_geom(p);
   hipStream_t st = (hipStream_t)stream;
   double* tile_bins = (double*)ws;
   const double rc2 = p->r_cut * p->r_cut;
@@ -337,29 +447,94 @@ extern "C" int md_eam_backward(const md_batch* b, const md_eam* p, md_precision 
     const dim3 grid(md_grid_blocks(b->n_tiles)), block(64 * L);
     const int nw = 64 * L / MD_WAVE, n_hot = g.n_phi + g.n_rho;
     g.stride = n_hot + (36 - n_hot % 32) % 32;  // copies start 8 banks apart
+    const size_t extra = jac ? MD_TILE : 0;
     auto lds_of = [&](int c) {
-      return ((size_t)nw * ((size_t)c * g.stride + g.n_emb) + g.n_rho) * sizeof(double);
+      return ((size_t)nw * ((size_t)c * g.stride + g.n_emb) + g.n_rho + extra) * sizeof(double);
     };
     g.copies = MD_ADJ_COPIES;
     while (g.copies > 1 && lds_of(g.copies) > MD_ADJ_LDS) g.copies >>= 1;
     const size_t lds = lds_of(g.copies);
     if (lds > 65536) return MD_ERR_ARG;  // fewer lanes per atom, or fewer coefficients
-#define MD_ADJ_LAUNCH(LN)                                                                    \
-  MD_LAUNCH_TIMED(MD_KERNEL_EAM_ADJOINT, (k_eam_adjoint<LN, MD_ADJ_U>), grid, block, lds, st, \
-                  *b, (const double4*)pos, nl->neigh, nl->nneigh, npad, saved, grad_force, g,  \
-                  rc2, tile_bins, (md_ctl_dev*)ctl)
-    switch (L) {
-      case 1: MD_ADJ_LAUNCH(1); break;
-      case 2: MD_ADJ_LAUNCH(2); break;
-      case 4: MD_ADJ_LAUNCH(4); break;
-      case 8: MD_ADJ_LAUNCH(8); break;
-      default: MD_ADJ_LAUNCH(16); break;
+#define MD_ADJ_LAUNCH(LN, J)                                                                   \
+  MD_LAUNCH_TIMED(MD_KERNEL_EAM_ADJOINT, (k_eam_adjoint<LN, MD_ADJ_U, J>), grid, block, lds,    \
+                  st, *b, (const double4*)pos, nl->neigh, nl->nneigh, npad, saved, jac,         \
+                  grad_force, g, rc2, tile_bins, (md_ctl_dev*)ctl)
+#define MD_ADJ_LAUNCH_L(J)                \
+  switch (L) {                            \
+    case 1: MD_ADJ_LAUNCH(1, J); break;   \
+    case 2: MD_ADJ_LAUNCH(2, J); break;   \
+    case 4: MD_ADJ_LAUNCH(4, J); break;   \
+    case 8: MD_ADJ_LAUNCH(8, J); break;   \
+    default: MD_ADJ_LAUNCH(16, J); break; \
+  }
+    if (jac) {
+      MD_ADJ_LAUNCH_L(true);
+    } else {
+      MD_ADJ_LAUNCH_L(false);
     }
+#undef MD_ADJ_LAUNCH_L
 #undef MD_ADJ_LAUNCH
     MD_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_adj_reduce, dim3(g.n_bins), dim3(256), 0, st, tile_bins, b->n_tiles,
                      g.n_bins, grad_coef);
+  MD_LAUNCH_CHECK();
+  return MD_OK;
+}
+
+bool jac_ok(const md_eam* p) {
+  return p && p->rho.ncoef >= 6 && p->rho.ncoef <= MD_JAC_MAX_COEF && p->rho.h > 0.0 &&
+         p->r_cut > 0.0;
+}
+
+}  // namespace
+
+extern "C" int md_eam_backward(const md_batch* b, const md_eam* p, md_precision prec,
+                               const double* pos, const md_nlist* nl, const double* saved,
+                               const double* grad_force, double* grad_coef, void* ws, void* ctl,
+                               void* stream) {
+  return backward(b, p, prec, pos, nl, saved, nullptr, grad_force, grad_coef, ws, ctl, stream);
+}
+
+extern "C" int md_eam_backward_jac(const md_batch* b, const md_eam* p, md_precision prec,
+                                   const double* pos, const md_nlist* nl, const double* saved,
+                                   const double* jac, const double* grad_force,
+                                   double* grad_coef, void* ws, void* ctl, void* stream) {
+  if (!jac) return MD_ERR_ARG;
+  return backward(b, p, prec, pos, nl, saved, jac, grad_force, grad_coef, ws, ctl, stream);
+}
+
+extern "C" size_t md_density_jacobian_bytes(const md_batch* b, const md_eam* p) {
+  if (!b || b->n_atoms < 0 || !jac_ok(p)) return 0;
+  return md_align256(sizeof(double) * (size_t)b->n_atoms * p->rho.ncoef);
+}
+
+extern "C" int md_eam_density_jacobian(const md_batch* b, const md_eam* p, const double* pos,
+                                       const md_nlist* nl, double* jac, void* ctl,
+                                       void* stream) {
+  if (!md_batch_ok(b)) return MD_ERR_ARG;
+  if (!jac_ok(p) || !pos || !nl || !nl->neigh || !nl->nneigh || !jac || !ctl) return MD_ERR_ARG;
+  if (!lanes_ok(nl)) return MD_ERR_ARG;
+  if (b->n_tiles == 0) return MD_OK;
+  const int L = nl->lanes;
+  const AdjGeom g = adj_geom(p);
+  const dim3 grid(md_grid_blocks(b->n_tiles)), block(64 * L);
+  const size_t lds = (size_t)MD_TILE * g.n_rho * sizeof(double);
+  hipStream_t st = (hipStream_t)stream;
+  const double rc2 = p->r_cut * p->r_cut;
+  const int npad = md_npad(b->n_atoms);
+#define MD_JAC_LAUNCH(LN)                                                                    \
+  hipLaunchKernelGGL((k_density_jacobian<LN, MD_ADJ_U>), grid, block, lds, st, *b,           \
+                     (const double4*)pos, nl->neigh, nl->nneigh, npad, g, rc2, jac,         \
+                     (md_ctl_dev*)ctl)
+  switch (L) {
+    case 1: MD_JAC_LAUNCH(1); break;
+    case 2: MD_JAC_LAUNCH(2); break;
+    case 4: MD_JAC_LAUNCH(4); break;
+    case 8: MD_JAC_LAUNCH(8); break;
+    default: MD_JAC_LAUNCH(16); break;
+  }
+#undef MD_JAC_LAUNCH
   MD_LAUNCH_CHECK();
   return MD_OK;
 }

@@ -23,7 +23,7 @@ class SnapshotBatch:
     """All snapshots as one md_batch (one box per snapshot), binned and listed once."""
 
     def __init__(self, snapshots, r_ns, precision=N.MD_FP64, lanes=4, max_neigh=128,
-                 device="cuda"):
+                 device="cuda", density_jacobian=True):
         boxes = [s.box for s in snapshots]
         counts = [s.pos.shape[0] for s in snapshots]
         pos = np.concatenate([s.pos for s in snapshots], axis=0)
@@ -38,6 +38,10 @@ class SnapshotBatch:
         self.saved = torch.zeros((3, self.n), dtype=torch.float64, device=device)
         self.bws = None
         self.lws = None  # md_force_loss workspace
+        # the positions never change, so d rhobar / d c_rho (n x n_rho FP64) is computed once
+        # per rho grid and the adjoint reads it instead of visiting every list a second time
+        self.use_jac = bool(density_jacobian)
+        self._jac, self._jac_key = None, None
         ids = self.state.id.long()
         # current (cell) order -> original order permutation, for the caller's references
         self.order_ids = ids
@@ -69,7 +73,18 @@ class SnapshotBatch:
         if self.bws is None or self.bws.numel() < nb:
             self.bws = torch.zeros(max(nb, 1), dtype=torch.uint8, device=self.state.pos.device)
         return md.md_eam_backward(self.state, pot, self.nl, self.saved if saved is None else saved,
-                                  g, ws=self.bws)
+                                  g, ws=self.bws, jac=self.jacobian(pot))
+
+    def jacobian(self, pot: md.EAMPotential):
+        """The density Jacobian for pot's rho grid and cutoff (kept), or None if not used."""
+        if not self.use_jac:
+            return None
+        r = pot.c.rho
+        key = (r.x_lo, r.h, r.ncoef, pot.c.r_cut)
+        if self._jac_key != key:
+            self._jac = md.md_eam_density_jacobian(self.state, pot, self.nl)
+            self._jac_key = key
+        return self._jac
 
 
 def _split(pot, c):

@@ -474,9 +474,28 @@ def md_force_loss(force, f_ref, precision, grad_force=None, ws=None, stream=None
     return loss
 
 
+def md_eam_density_jacobian(st: State, pot: EAMPotential, nl: NeighborList, out=None,
+                            stream=None):
+    """d rhobar_i / d c_rho_k of the current positions as an [n, n_rho] FP64 tensor."""
+    L = N.lib()
+    n, n_rho = st.plan.n_atoms, pot.coef[1].shape[0]
+    nb = int(L.md_density_jacobian_bytes(C.byref(st.plan.c), C.byref(pot.c)))
+    if nb == 0 and n > 0:
+        raise ValueError("density Jacobian not available for %d rho coefficients" % n_rho)
+    if out is None:
+        out = torch.empty((n, n_rho), dtype=torch.float64, device=st.pos.device)
+    elif out.dtype != torch.float64 or tuple(out.shape) != (n, n_rho) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [%d, %d] float64 tensor" % (n, n_rho))
+    check(L.md_eam_density_jacobian(C.byref(st.plan.c), C.byref(pot.c), _ptr(st.pos),
+                                    C.byref(nl.c), _ptr(out), _ptr(st.ctl), _stream(stream)),
+          "md_eam_density_jacobian")
+    return out
+
+
 def md_eam_backward(st: State, pot: EAMPotential, nl: NeighborList, saved, grad_force, ws=None,
-                    stream=None):
-    """grad_force: [3, n] FP64 cotangent in the current atom order.  Returns [n_coef total]."""
+                    stream=None, jac=None):
+    """grad_force: [3, n] FP64 cotangent in the current atom order.  Returns [n_coef total].
+    jac: the density Jacobian of the same positions (md_eam_density_jacobian), if kept."""
     L = N.lib()
     nb = int(L.md_backward_workspace_bytes(C.byref(st.plan.c), C.byref(pot.c)))
     if nb == 0:
@@ -484,7 +503,13 @@ def md_eam_backward(st: State, pot: EAMPotential, nl: NeighborList, saved, grad_
     if ws is None or ws.numel() < nb:
         ws = torch.zeros(nb, dtype=torch.uint8, device=st.pos.device)
     out = torch.empty(sum(c.shape[0] for c in pot.coef), dtype=torch.float64, device=st.pos.device)
-    check(L.md_eam_backward(C.byref(st.plan.c), C.byref(pot.c), st.precision, _ptr(st.pos),
-                            C.byref(nl.c), _ptr(saved), _ptr(grad_force), _ptr(out), _ptr(ws),
-                            _ptr(st.ctl), _stream(stream)), "md_eam_backward")
+    if jac is None:
+        check(L.md_eam_backward(C.byref(st.plan.c), C.byref(pot.c), st.precision, _ptr(st.pos),
+                                C.byref(nl.c), _ptr(saved), _ptr(grad_force), _ptr(out),
+                                _ptr(ws), _ptr(st.ctl), _stream(stream)), "md_eam_backward")
+    else:
+        check(L.md_eam_backward_jac(C.byref(st.plan.c), C.byref(pot.c), st.precision,
+                                    _ptr(st.pos), C.byref(nl.c), _ptr(saved), _ptr(jac),
+                                    _ptr(grad_force), _ptr(out), _ptr(ws), _ptr(st.ctl),
+                                    _stream(stream)), "md_eam_backward_jac")
     return out

@@ -121,7 +121,7 @@ def test_batched_graph_replay_equals_eager(md):
 # ----------------------------------------------------------------------------
 # adjoint
 # ----------------------------------------------------------------------------
-def _fm_problem(md, n_snap=3, cells=5, prec=0, lanes=4):
+def _fm_problem(md, n_snap=3, cells=5, prec=0, lanes=4, jac=True):
     from paper_2511_22951_amd import fm
     tab = mi.force_matching_tables()
     noise = mi.coefficient_noise()
@@ -136,7 +136,8 @@ def _fm_problem(md, n_snap=3, cells=5, prec=0, lanes=4):
     nz = torch.as_tensor(noise, device="cuda")
     pot = md.EAMPotential(fits[0] * nz[:64], fits[1] * nz[64:128], fits[2] * nz[128:],
                           tab.rho.x_lo, tab.rho.h, tab.emb.x_lo, tab.emb.h, mi.EAM_CU.r_cut)
-    batch = fm.SnapshotBatch(snaps, mi.EAM_CU.r_cut + 0.3, precision=prec, lanes=lanes)
+    batch = fm.SnapshotBatch(snaps, mi.EAM_CU.r_cut + 0.3, precision=prec, lanes=lanes,
+                             density_jacobian=jac)
     return snaps, osnaps, grids, c_or, pot, batch
 
 
@@ -201,18 +202,46 @@ def test_adjoint_vjp_matches_oracle(md):
     assert np.array_equal(got, got2)  # run-to-run bitwise reproducible
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 8, 16])
-def test_adjoint_vjp_every_lane_count(md, lanes):
+@pytest.mark.parametrize("jac", [False, True])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
+def test_adjoint_vjp_every_lane_count(md, lanes, jac):
     """The adjoint at every lane count the list allows (a different number of bin copies
-    per wavefront fits the LDS at each: 8, 8, 4, 2; 16 lanes leave about five list entries
-    per lane) against the oracle's chain-rule VJP, 1e-10 relative."""
-    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, n_snap=2, lanes=lanes)
+    per wavefront fits the LDS at each: 8, 8, 8, 4, 2; 16 lanes leave about five list
+    entries per lane), with the second list visit and with the density Jacobian, against the
+    oracle's chain-rule VJP, 1e-10 relative."""
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, n_snap=2, lanes=lanes, jac=jac)
     G = [mi.random_cotangent(len(s.pos), seed=60 + k) for k, s in enumerate(snaps)]
     want = np.concatenate(oadj.vjp(osnaps, c_or, grids, G))
     batch.forces(pot, saved=True)
     got = batch.backward(pot, batch.to_current_order(np.concatenate(G))).cpu().numpy()
     batch.state.check_flags()
     assert np.max(np.abs(got - want)) < 1e-10 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 16])
+def test_density_jacobian_matches_oracle(md, lanes):
+    """md_eam_density_jacobian against the oracle's d rhobar / d c_rho (rows in the batch's
+    current order), 1e-12 of the largest entry, and bitwise reproducible."""
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, lanes=lanes)
+    jac = md.md_eam_density_jacobian(batch.state, pot, batch.nl)
+    batch.state.check_flags()
+    want = np.concatenate([oadj.density_jacobian(s, grids[1]) for s in osnaps])
+    got = jac.cpu().numpy()[np.argsort(batch.order_ids.cpu().numpy())]
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    assert torch.equal(md.md_eam_density_jacobian(batch.state, pot, batch.nl), jac)
+
+
+def test_backward_with_jacobian_equals_second_visit(md):
+    """Both forms of the adjoint on the same forward state and cotangent: equal to 1e-13 of
+    the largest gradient entry."""
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, jac=False)
+    G = batch.to_current_order(np.concatenate(
+        [mi.random_cotangent(len(s.pos), seed=80 + k) for k, s in enumerate(snaps)]))
+    batch.forces(pot, saved=True)
+    a = batch.backward(pot, G).cpu().numpy()
+    jac = md.md_eam_density_jacobian(batch.state, pot, batch.nl)
+    b = md.md_eam_backward(batch.state, pot, batch.nl, batch.saved, G, jac=jac).cpu().numpy()
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
 
 
 def test_force_matching_gradient_matches_oracle_and_fd(md):

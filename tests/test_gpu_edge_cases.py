@@ -5,7 +5,7 @@
                            records to the fixed-point rounding of per-block sums); the
                            empty box's record is exactly zero; EAM and LJ, FP64 and FP32
   empty batch              n_atoms = 0: every entry point returns MD_OK and writes nothing
-                           (md_profiles, md_eam_backward and md_force_loss write zeros)
+                           (md_profiles, both adjoints and md_force_loss write zeros)
   lone atom                no neighbours: LJ force and energy exactly zero; EAM density 0
                            lies below the embedding table, so MD_ERR_TABLE_RANGE is reported
                            (the oracle flags the same atom)
@@ -134,6 +134,12 @@ def test_empty_batch_entry_points_write_nothing():
     assert L.md_eam_backward(b, C.byref(fm.c), N.MD_FP64, P(buf["pos"]), C.byref(nl),
                              P(buf["saved"]), P(buf["force"]), P(buf["grad"]), P(ws), P(ctl),
                              s) == ok
+    assert L.md_eam_density_jacobian(b, C.byref(fm.c), P(buf["pos"]), C.byref(nl),
+                                     P(buf["out"]), P(ctl), s) == ok
+    g2 = torch.full((ncoef + 4,), sentinel, dtype=torch.float64, device="cuda")
+    assert L.md_eam_backward_jac(b, C.byref(fm.c), N.MD_FP64, P(buf["pos"]), C.byref(nl),
+                                 P(buf["saved"]), P(buf["out"]), P(buf["force"]), P(g2), P(ws),
+                                 P(ctl), s) == ok
     lo = torch.full((2,), sentinel, dtype=torch.float64, device="cuda")
     assert ws.numel() >= L.md_force_loss_workspace_bytes(0)
     for prec in (N.MD_FP64, N.MD_FP32):
@@ -143,6 +149,7 @@ def test_empty_batch_entry_points_write_nothing():
     assert torch.all(buf["out"][:n_bins * N.MD_PROF_LEN] == 0.0)
     assert torch.all(buf["out"][n_bins * N.MD_PROF_LEN:] == sentinel)
     assert torch.all(buf["grad"][:ncoef] == 0.0) and torch.all(buf["grad"][ncoef:] == sentinel)
+    assert torch.all(g2[:ncoef] == 0.0) and torch.all(g2[ncoef:] == sentinel)
     flags = (C.c_int * 4)()
     assert L.md_read_flags(P(ctl), flags, s) == ok
     assert list(flags) == [0, 0, 0, 0]  # flags, step, rebuilds, longest list

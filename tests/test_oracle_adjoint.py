@@ -122,3 +122,22 @@ def test_force_loss_agrees_with_loss_and_cotangents(problem):
     assert abs(L - adj.loss(snaps, c, grids, f_ref)) <= 1e-15 * L
     for g, g2 in zip(G, adj.cotangents(snaps, c, grids, f_ref)):
         assert np.array_equal(g, g2)
+
+
+def test_density_jacobian_pins(problem):
+    """density_jacobian: R c_rho reproduces rhobar of the force evaluation (rhobar is linear in
+    the density coefficients); a unit step in one coefficient changes rhobar by that column;
+    each row sums to the number of pairs of the atom inside the grid (partition of unity)."""
+    snaps, snaps_in, c, c0, grids, f_ref = problem
+    g_rho = grids[1]
+    for s in snaps:
+        R = adj.density_jacobian(s, g_rho)
+        rb = adj.forces(s, c, grids)[1]
+        assert np.max(np.abs(R @ c[1] - rb)) <= 1e-12 * np.max(np.abs(rb))
+        for k in (15, 30, 45):
+            cp = [c[0], c[1].copy(), c[2]]
+            cp[1][k] += 1.0
+            d = adj.forces(s, cp, grids)[1] - rb
+            assert np.max(np.abs(d - R[:, k])) < 1e-11
+        npairs = np.bincount(s.i, minlength=s.n)
+        assert np.allclose(R.sum(axis=1), npairs, rtol=0, atol=1e-12)
