@@ -408,6 +408,16 @@ size_t md_density_jacobian_bytes(const md_batch* b, const md_eam* p);
 int md_eam_density_jacobian(const md_batch* b, const md_eam* p, const double* pos,
                             const md_nlist* nl, double* jac, void* ctl, void* stream);
 
+/* md_eam_forces (no kick, drift or energy records) for fixed positions whose density
+ * Jacobian `jac` (md_eam_density_jacobian: same positions, list, rho grid and r_cut) is
+ * kept: the density pass becomes rhobar = jac c_rho, one row per atom, in place of a
+ * visit of every list; the force pass is the same.  force, saved, ws and the table as in
+ * md_eam_forces.  rhobar and so F', F'' agree with md_eam_forces to rounding (FP64; in
+ * FP32 to the resampled tables' error).  MD_ERR_ARG for a NULL jac or rho.ncoef > 128. */
+int md_eam_forces_jac(const md_batch* b, const md_eam* p, md_precision prec, const void* table,
+                      const double* pos, const md_nlist* nl, const double* jac, void* force,
+                      double* saved, void* ws, void* ctl, void* stream);
+
 /* Force-matching loss (the mean squared force error over all atoms of all boxes)
  * and its cotangent: L = (1/n) sum_i |F_i - F_ref,i|^2 and G = dL/dF = (2/n)(F - F_ref),
  * the G that md_eam_backward takes.  force: [3][n] as md_eam_forces writes it (float for

@@ -140,6 +140,8 @@ _SIGS = {
                                  _vp, _vp]),
     "md_density_jacobian_bytes": (_sz, [_P(Batch), _P(EAM)]),
     "md_eam_density_jacobian": (_i, [_P(Batch), _P(EAM), _vp, _P(NList), _vp, _vp, _vp]),
+    "md_eam_forces_jac": (_i, [_P(Batch), _P(EAM), _i, _vp, _vp, _P(NList), _vp, _vp, _vp, _vp,
+                               _vp, _vp]),
     "md_force_loss_workspace_bytes": (_sz, [_i]),
     "md_force_loss": (_i, [_i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
     "md_atom_observables": (_i, [_P(Batch), _P(EAM), _P(LJ), _vp, _P(NList), _vp, _vp, _vp,

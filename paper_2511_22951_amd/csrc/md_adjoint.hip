@@ -261,7 +261,8 @@ __global__ __launch_bounds__(64 * LANES) void k_eam_adjoint(
     for (int k = lane; k < g.n_rho; k += MD_WAVE) {
       double acc = 0.0;
       for (int a2 = wid; a2 < T.count; a2 += nw)
-        acc = fma(s_w[a2], jac[(size_t)(T.first + a2) * g.n_rho + k], acc);
+        acc = fma(s_w[a2], __builtin_nontemporal_load(jac + (size_t)(T.first + a2) * g.n_rho + k),
+                  acc);
       rho0[k] += acc;
     }
   }

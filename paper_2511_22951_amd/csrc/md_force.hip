@@ -544,6 +544,63 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_density_f64(MD_EAM_DENSITY_ARGS(
 }
 #undef MD_EAM_DENSITY_ARGS
 
+// Density pass for fixed positions whose density Jacobian jac[i][k] = d rhobar_i /
+// d c_rho_k is kept: rhobar_i = sum_k c_rho_k jac[i][k].  Each wavefront takes 64
+// consecutive atoms, four at a time: a group of 16 lanes reads one atom's row (lane q
+// entries q, q + 16, ...: one cache line per group and load) and adds it up by a group
+// butterfly; then the embedding as in the pair-loop pass with one atom per lane.
+// n_rho <= 128.
+template <typename R>
+__global__ __launch_bounds__(MD_ATOM_BLOCK) void k_eam_density_jac(
+    int n, double4* pos, const double* __restrict__ jac, const double* __restrict__ c_rho,
+    int n_rho, const R* __restrict__ etab, TabGeom g, double* saved, uint4* rec,
+    md_ctl_dev* ctl) {
+  __shared__ double s_rho[MD_ATOM_BLOCK];
+  const int lane = threadIdx.x & (MD_WAVE - 1);
+  double* wrho = s_rho + (threadIdx.x - lane);  // this wavefront's 64 sums
+  const int a0 = ((blockIdx.x * blockDim.x + threadIdx.x) / MD_WAVE) * MD_WAVE;
+  if (a0 >= n) return;  // whole wavefronts
+  const int na = min(MD_WAVE, n - a0);
+  const int grp = lane >> 4, q = lane & 15;
+  double c[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) c[j] = q + 16 * j < n_rho ? c_rho[q + 16 * j] : 0.0;
+#pragma unroll 2
+  for (int a = grp; a < na; a += 4) {
+    const double* row = jac + (size_t)(a0 + a) * n_rho;
+    double v = 0.0;
+    // streamed once per pass: kept out of the way of the force pass's cached records
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (q + 16 * j < n_rho) v = fma(c[j], __builtin_nontemporal_load(row + q + 16 * j), v);
+    v = md_group_sum<16>(v);
+    if (q == 0) wrho[a] = v;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const double mine = lane < na ? wrho[lane] : 0.0;
+  bool oor = false;
+  if (lane < na) {
+    const int i = a0 + lane;
+    const R rho = (R)mine;
+    R tt;
+    const R u = (rho - (R)g.e_lo) * (R)g.e_inv_h;
+    if (u < (R)0 || u > (R)g.ne) oor = true;
+    const int k = tab_index<R>(rho, (R)g.e_lo, (R)g.e_inv_h, g.ne, tt, oor);
+    const R* row = etab + (size_t)k * MD_ETAB_W;
+    const R F1 = (row[6] * tt + row[5]) * tt + row[4];
+    store_fp<R>(pos, i, F1);
+    if (rec) reinterpret_cast<uint32_t*>(rec + i)[3] = __float_as_uint((float)F1);
+    if (saved) {
+      saved[i] = (double)rho;
+      saved[n + i] = (double)F1;
+      saved[2 * n + i] = (double)(row[8] * tt + row[7]);
+    }
+  }
+  if (__any(oor)) {
+    if (lane == 0) md_flag(ctl, MD_FLAG_TABLE_RANGE);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // EAM pass 2: f_i = sum_j [phi'(r) + (F'_i + F'_j) rho'(r)] (r_j - r_i) / r,
 // virial, trailing kick and kinetic energy.
@@ -962,9 +1019,10 @@ int allow_big_lds(const void* fn, size_t bytes) {
 
 template <typename R, int LANES>
 int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_table_layout& TL,
-                const double* pos, const md_nlist& nl, void* force, double* saved, double* vel,
-                double inv_mass, double half_dt, const DriftArgs& dr, long long* ev, int ev_cap,
-                double* partial, uint4* rec_ws, md_ctl_dev* ctl, hipStream_t st) {
+                const double* pos, const md_nlist& nl, const double* jac, void* force,
+                double* saved, double* vel, double inv_mass, double half_dt, const DriftArgs& dr,
+                long long* ev, int ev_cap, double* partial, uint4* rec_ws, md_ctl_dev* ctl,
+                hipStream_t st) {
   // FP32: fixed-point records, carried over (md_drift.rec_in) or in the workspace
   uint4* rec = std::is_same<R, float>::value ? (dr.rec_in ? dr.rec_in : rec_ws) : nullptr;
   TabGeom g;
@@ -990,7 +1048,12 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
   const size_t lds_f = ld ? (size_t)rows * MD_FTAB_W * sizeof(R) : 0;
 #define MD_EAM_LAUNCH(EVB, TL_, E_, TH_)                                                          \
   do {                                                                                         \
-    if constexpr (std::is_same<R, float>::value) {                                             \
+    if (jac) {                                                                                 \
+      MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_jac<R>),                           \
+                      dim3((b.n_atoms + MD_ATOM_BLOCK - 1) / MD_ATOM_BLOCK), dim3(MD_ATOM_BLOCK), \
+                      0, st, b.n_atoms, (double4*)pos, jac, p.rho.coef, p.rho.ncoef, etab, g,  \
+                      saved, rec, ctl);                                                        \
+    } else if constexpr (std::is_same<R, float>::value) {                                      \
       if ((st_ = allow_big_lds((const void*)k_eam_density_f32<LANES, EVB, TL_, E_>, lds_d)))     \
         return st_;                                                                            \
       MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_f32<LANES, EVB, TL_, E_>), grid, block, \
@@ -1133,7 +1196,7 @@ static int eam_forces(const md_batch* b, const md_eam* p, md_precision prec, con
                       const double* pos, const md_nlist* nl, void* force, double* saved,
                       double* vel, double inv_mass, double half_dt, const md_drift* drift,
                       long long* ev, int ev_cap, double* partial, uint4* rec, bool ws_ok,
-                      void* ctl, void* stream) {
+                      void* ctl, void* stream, const double* jac = nullptr) {
   if (!md_batch_ok(b) || !md_eam_ok(p) || !table || !pos || !nlist_ok(nl) || !force || !ws_ok ||
       !ctl)
     return MD_ERR_ARG;
@@ -1151,12 +1214,12 @@ static int eam_forces(const md_batch* b, const md_eam* p, md_precision prec, con
   int rc = MD_OK;
   if (prec == MD_FP32) {
     MD_DISPATCH_LANES(nl->lanes, (rc = launch_eam<float, L_>(*b, *p, (const char*)table, TL, pos,
-                                                             *nl, force, saved, vel, inv_mass,
+                                                             *nl, jac, force, saved, vel, inv_mass,
                                                              half_dt, dr, (long long*)ev, ev_cap,
                                                              partial, rec, c, st)));
   } else {
     MD_DISPATCH_LANES(nl->lanes, (rc = launch_eam<double, L_>(*b, *p, (const char*)table, TL, pos,
-                                                              *nl, force, saved, vel, inv_mass,
+                                                              *nl, jac, force, saved, vel, inv_mass,
                                                               half_dt, dr, (long long*)ev, ev_cap,
                                                               partial, rec, c, st)));
   }
@@ -1179,6 +1242,22 @@ extern "C" int md_eam_forces(const md_batch* b, const md_eam* p, md_precision pr
   }
   return eam_forces(b, p, prec, table, pos, nl, force, saved, vel, inv_mass, half_dt, drift, ev,
                     ev_cap, partial, rec, ws != nullptr, ctl, stream);
+}
+
+extern "C" int md_eam_forces_jac(const md_batch* b, const md_eam* p, md_precision prec,
+                                 const void* table, const double* pos, const md_nlist* nl,
+                                 const double* jac, void* force, double* saved, void* ws,
+                                 void* ctl, void* stream) {
+  if (!jac || !p || p->rho.ncoef > 128) return MD_ERR_ARG;
+  double* partial = nullptr;
+  uint4* rec = nullptr;
+  if (ws && b && b->n_atoms >= 0 && b->n_tiles >= 0) {
+    const md_ws_layout WL = md_ws_plan(b);
+    partial = (double*)((char*)ws + WL.partial);
+    rec = (uint4*)((char*)ws + WL.rec);
+  }
+  return eam_forces(b, p, prec, table, pos, nl, force, saved, nullptr, 0.0, 0.0, nullptr, nullptr,
+                    0, partial, rec, ws != nullptr, ctl, stream, jac);
 }
 
 // ---------------------------------------------------------------------------

@@ -39,9 +39,10 @@ class SnapshotBatch:
         self.bws = None
         self.lws = None  # md_force_loss workspace
         # the positions never change, so d rhobar / d c_rho (n x n_rho FP64) is computed once
-        # per rho grid and the adjoint reads it instead of visiting every list a second time
+        # per rho grid; the density pass (rhobar = jac c_rho) and the adjoint read it instead
+        # of visiting every list
         self.use_jac = bool(density_jacobian)
-        self._jac, self._jac_key = None, None
+        self._jac = {}  # (rho x_lo, h, ncoef, r_cut) -> Jacobian, or None where not available
         ids = self.state.id.long()
         # current (cell) order -> original order permutation, for the caller's references
         self.order_ids = ids
@@ -51,14 +52,21 @@ class SnapshotBatch:
         t = torch.as_tensor(np.asarray(a, np.float64), device=self.state.pos.device)
         return t[self.order_ids].t().contiguous()
 
+    def _forces(self, pot: md.EAMPotential, saved):
+        jac = self.jacobian(pot)
+        if jac is None:
+            md.md_eam_forces(self.state, pot, self.nl, saved=saved)
+        else:
+            md.md_eam_forces_jac(self.state, pot, self.nl, jac, saved=saved)
+
     def forces(self, pot: md.EAMPotential, saved=True):
-        md.md_eam_forces(self.state, pot, self.nl, saved=self.saved if saved else None)
+        self._forces(pot, self.saved if saved else None)
         return self.state.force.double()
 
     def loss(self, pot: md.EAMPotential, f_ref, saved, grad_force):
         """Forces at pot's coefficients ({rhobar, F', F''} into saved), then the loss against
         f_ref ([3, n] FP64) as a 0-dim device tensor and its cotangent into grad_force."""
-        md.md_eam_forces(self.state, pot, self.nl, saved=saved)
+        self._forces(pot, saved)
         if self.lws is None:
             nb = int(N.lib().md_force_loss_workspace_bytes(self.n))
             self.lws = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.state.pos.device)
@@ -76,15 +84,16 @@ class SnapshotBatch:
                                   g, ws=self.bws, jac=self.jacobian(pot))
 
     def jacobian(self, pot: md.EAMPotential):
-        """The density Jacobian for pot's rho grid and cutoff (kept), or None if not used."""
+        """The density Jacobian for pot's rho grid and cutoff (kept), or None if not used or
+        not available (more than 128 rho coefficients)."""
         if not self.use_jac:
             return None
         r = pot.c.rho
         key = (r.x_lo, r.h, r.ncoef, pot.c.r_cut)
-        if self._jac_key != key:
-            self._jac = md.md_eam_density_jacobian(self.state, pot, self.nl)
-            self._jac_key = key
-        return self._jac
+        if key not in self._jac:
+            nb = int(N.lib().md_density_jacobian_bytes(C.byref(self.plan.c), C.byref(pot.c)))
+            self._jac[key] = md.md_eam_density_jacobian(self.state, pot, self.nl) if nb else None
+        return self._jac[key]
 
 
 def _split(pot, c):

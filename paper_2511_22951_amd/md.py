@@ -315,6 +315,21 @@ def md_eam_forces(st: State, pot: EAMPotential, nl: NeighborList, table=None, sa
           "md_eam_forces")
 
 
+def md_eam_forces_jac(st: State, pot: EAMPotential, nl: NeighborList, jac, table=None,
+                      saved=None, stream=None):
+    """Forces of fixed positions with the density from the kept density Jacobian jac
+    ([n, n_rho] FP64, md_eam_density_jacobian of the same positions and list)."""
+    table = pot.table(st.precision) if table is None else table
+    n_rho = pot.coef[1].shape[0]
+    if jac.dtype != torch.float64 or tuple(jac.shape) != (st.plan.n_atoms, n_rho) or \
+            not jac.is_contiguous():
+        raise ValueError("jac must be a contiguous [n, n_rho] float64 tensor")
+    check(N.lib().md_eam_forces_jac(C.byref(st.plan.c), C.byref(pot.c), st.precision, _ptr(table),
+                                    _ptr(st.pos), C.byref(nl.c), _ptr(jac), _ptr(st.force),
+                                    _ptr(saved), _ptr(st.ws), _ptr(st.ctl), _stream(stream)),
+          "md_eam_forces_jac")
+
+
 def md_eam_forces_noalloc(st: State, pot: EAMPotential, nl: NeighborList, table=None,
                           saved=None, inv_mass=0.0, half_dt=0.0, kick=False, ev=None, ev_cap=1,
                           drift=None, stream=None):

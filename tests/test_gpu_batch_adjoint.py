@@ -231,6 +231,40 @@ def test_density_jacobian_matches_oracle(md, lanes):
     assert torch.equal(md.md_eam_density_jacobian(batch.state, pot, batch.nl), jac)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_forces_with_jacobian_match_pair_pass(md, prec):
+    """md_eam_forces_jac (density as jac c_rho) against md_eam_forces on the same batch and
+    against the oracle.  FP64: forces within 1e-12 and {rhobar, F', F''} within 1e-13 of their
+    largest entries, forces within 1e-10 of the oracle's.  FP32 (the force pass's resampled
+    r^2 tables of these 64-coefficient splines): both forms within 5e-5 (Frobenius) of the
+    oracle's forces, rhobar within 1e-5 of the pair pass's (the pair pass sums the resampled
+    FP32 density table, the Jacobian form evaluates the spline in FP64)."""
+    snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, prec=prec, jac=False)
+    st, nl = batch.state, batch.nl
+    s0 = torch.empty((3, batch.n), dtype=torch.float64, device="cuda")
+    md.md_eam_forces(st, pot, nl, saved=s0)
+    f0 = st.force.double().clone()
+    jac = md.md_eam_density_jacobian(st, pot, nl)
+    s1 = torch.empty_like(s0)
+    md.md_eam_forces_jac(st, pot, nl, jac, saved=s1)
+    f1 = st.force.double().clone()
+    st.check_flags()
+    order = np.argsort(batch.order_ids.cpu().numpy())
+    want = np.concatenate([oadj.forces(s, c_or, grids)[0] for s in osnaps])
+    got0 = f0.t().cpu().numpy()[order]
+    got1 = f1.t().cpu().numpy()[order]
+    if prec == 0:
+        fmax = f0.abs().max().item()
+        assert (f1 - f0).abs().max().item() <= 1e-12 * fmax
+        for r in range(3):
+            assert (s1[r] - s0[r]).abs().max().item() <= 1e-13 * s0[r].abs().max().item()
+        assert np.max(np.abs(got1 - want)) <= 1e-10 * np.max(np.abs(want))
+    else:
+        e0, e1 = (np.linalg.norm(g - want) / np.linalg.norm(want) for g in (got0, got1))
+        assert e0 <= 5e-5 and e1 <= 5e-5, (e0, e1)
+        assert (s1[0] - s0[0]).abs().max().item() <= 1e-5 * s0[0].abs().max().item()
+
+
 def test_backward_with_jacobian_equals_second_visit(md):
     """Both forms of the adjoint on the same forward state and cotangent: equal to 1e-13 of
     the largest gradient entry."""

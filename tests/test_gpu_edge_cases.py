@@ -136,6 +136,10 @@ def test_empty_batch_entry_points_write_nothing():
                              s) == ok
     assert L.md_eam_density_jacobian(b, C.byref(fm.c), P(buf["pos"]), C.byref(nl),
                                      P(buf["out"]), P(ctl), s) == ok
+    for prec in (N.MD_FP64, N.MD_FP32):
+        assert L.md_eam_forces_jac(b, C.byref(fm.c), prec, P(fm.table(prec)), P(buf["pos"]),
+                                   C.byref(nl), P(buf["out"]), P(buf["force"]), P(buf["saved"]),
+                                   P(ws), P(ctl), s) == ok
     g2 = torch.full((ncoef + 4,), sentinel, dtype=torch.float64, device="cuda")
     assert L.md_eam_backward_jac(b, C.byref(fm.c), N.MD_FP64, P(buf["pos"]), C.byref(nl),
                                  P(buf["saved"]), P(buf["out"]), P(buf["force"]), P(g2), P(ws),
