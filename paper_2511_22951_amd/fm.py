@@ -96,11 +96,6 @@ class SnapshotBatch:
         return self._jac[key]
 
 
-def _split(pot, c):
-    n0, n1 = pot.coef[0].shape[0], pot.coef[1].shape[0]
-    return c[:n0], c[n0:n0 + n1], c[n0 + n1:]
-
-
 class EAMForces(torch.autograd.Function):
     """forces = EAMForces.apply(coef, batch, potential): coef is the concatenated
     (phi | rho | F) coefficient vector; the result is [3, n] in the batch's current order.
@@ -113,7 +108,7 @@ class EAMForces(torch.autograd.Function):
     @staticmethod
     def forward(ctx, coef, batch: SnapshotBatch, pot: md.EAMPotential):
         c = coef.detach().to(torch.float64).contiguous()
-        pot.set_coefficients(*_split(pot, c))
+        pot.set_coefficients_flat(c)
         f = batch.forces(pot, saved=True).clone()
         ctx.batch, ctx.pot = batch, pot
         ctx.coef = c.clone()
@@ -130,12 +125,12 @@ class EAMForces(torch.autograd.Function):
         else:
             # a later forward changed the coefficients: differentiate at this call's, then
             # put the later ones back (with their version, so their own backward stays direct)
-            later, later_version = torch.cat([c.clone() for c in pot.coef]), pot.version
-            pot.set_coefficients(*_split(pot, ctx.coef))
+            later, later_version = pot.coefficients_flat(), pot.version
+            pot.set_coefficients_flat(ctx.coef)
             try:
                 g = ctx.batch.backward(pot, grad_f, saved=ctx.saved)
             finally:
-                pot.set_coefficients(*_split(pot, later))
+                pot.set_coefficients_flat(later)
                 pot.version = later_version
         return g.to(ctx.coef_dtype), None, None
 
@@ -150,7 +145,7 @@ class ForceMatchingLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, coef, batch: SnapshotBatch, pot: md.EAMPotential, f_ref):
         c = coef.detach().to(torch.float64).contiguous()
-        pot.set_coefficients(*_split(pot, c))
+        pot.set_coefficients_flat(c)
         saved = torch.empty((3, batch.n), dtype=torch.float64, device=f_ref.device)
         G = torch.empty((3, batch.n), dtype=torch.float64, device=f_ref.device)
         loss = batch.loss(pot, f_ref, saved, G)
@@ -167,12 +162,12 @@ class ForceMatchingLoss(torch.autograd.Function):
         if pot.version == ctx.version:
             g = ctx.batch.backward(pot, ctx.G, saved=ctx.saved)
         else:
-            later, later_version = torch.cat([c.clone() for c in pot.coef]), pot.version
-            pot.set_coefficients(*_split(pot, ctx.coef))
+            later, later_version = pot.coefficients_flat(), pot.version
+            pot.set_coefficients_flat(ctx.coef)
             try:
                 g = ctx.batch.backward(pot, ctx.G, saved=ctx.saved)
             finally:
-                pot.set_coefficients(*_split(pot, later))
+                pot.set_coefficients_flat(later)
                 pot.version = later_version
         return (g * grad_loss).to(ctx.coef_dtype), None, None, None
 

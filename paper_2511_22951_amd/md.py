@@ -203,9 +203,13 @@ class EAMPotential:
 
     def __init__(self, c_phi, c_rho, c_emb, r_lo, r_h, e_lo, e_h, r_cut, device="cuda"):
         dev = torch.device(device)
-        self.coef = [torch.as_tensor(np.asarray(c, np.float64) if not torch.is_tensor(c) else c,
-                                     dtype=torch.float64, device=dev).contiguous()
-                     for c in (c_phi, c_rho, c_emb)]
+        parts = [torch.as_tensor(np.asarray(c, np.float64) if not torch.is_tensor(c) else c,
+                                 dtype=torch.float64, device=dev).reshape(-1)
+                 for c in (c_phi, c_rho, c_emb)]
+        # one buffer (phi | rho | F), so that a new coefficient vector is one copy
+        self._flat = torch.cat(parts).contiguous()
+        n0, n1 = parts[0].shape[0], parts[1].shape[0]
+        self.coef = [self._flat[:n0], self._flat[n0:n0 + n1], self._flat[n0 + n1:]]
         self.r_lo, self.r_h, self.e_lo, self.e_h = float(r_lo), float(r_h), float(e_lo), float(e_h)
         self.r_cut = float(r_cut)
         self.device = dev
@@ -233,12 +237,20 @@ class EAMPotential:
         for k, c in enumerate((c_phi, c_rho, c_emb)):
             if c is not None:
                 self.coef[k].copy_(torch.as_tensor(c, dtype=torch.float64))
-        self._tables = {}
         self.version += 1
-        self._build_struct()
+
+    def set_coefficients_flat(self, c):
+        """All coefficients at once from one (phi | rho | F) vector."""
+        self._flat.copy_(torch.as_tensor(c, dtype=torch.float64).reshape(-1))
+        self.version += 1
+
+    def coefficients_flat(self):
+        """A copy of the (phi | rho | F) coefficient vector."""
+        return self._flat.clone()
 
     def table(self, precision):
-        """Packed interval tables (md_eam_prepare), rebuilt after coefficient changes."""
+        """Packed interval tables (md_eam_prepare), prepared from the current coefficients on
+        every call (the buffer is kept: its size depends on the grids alone)."""
         if precision not in self._tables:
             nbytes = int(N.lib().md_eam_table_bytes(C.byref(self.c), precision))
             if nbytes == 0:
