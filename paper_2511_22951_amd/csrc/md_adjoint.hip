@@ -13,9 +13,12 @@
 // The F'' and beta' terms are the mixed second derivatives.
 //
 // One kernel visits each atom's list twice (the second visit needs the complete
-// tau_i).  Each wavefront accumulates into its own LDS bins; a block adds its
-// wavefronts' bins in wave order into per-tile partials, and a second kernel
-// adds the tile partials in tile order.  All sums are FP64.  Pair distances crowd
+// tau_i); where the density Jacobian sum_j beta_k(r_ij) = d rhobar_i / d c_rho_k of
+// the fixed positions is kept, the second visit is a product with its rows instead.
+// The same file holds that Jacobian's kernel and the force-matching loss.  Each
+// wavefront accumulates into its own LDS bins; a block adds its wavefronts' bins in
+// wave order into per-tile partials, and a second kernel adds the tile partials in
+// a fixed order.  All sums are FP64.  Pair distances crowd
 // around the neighbour shells, so many lanes of one atomic add hit the same phi or
 // rho bin and the LDS serialises them: each wavefront keeps several copies of those
 // bins (lane l adds into copy l mod copies), laid out to start on different banks.
