@@ -101,3 +101,33 @@ def test_noalloc_entry_point_rejects_oversize_batches(lib):
         st = lib.md_eam_forces_noalloc(C.byref(b), None, 1, None, None, None, None, None, None,
                                        0.0, 0.0, None, None, 1, None, None)
         assert st == N.MD_ERR_WORKSPACE
+
+
+def test_force_matching_entry_points_check_arguments_on_the_host(lib):
+    """The force-matching entry points reject malformed arguments with MD_ERR_ARG (or a zero
+    size) before any device work: a NULL Jacobian, more than 128 rho coefficients for the
+    Jacobian forms, a negative atom count or NULL outputs for the loss."""
+    from paper_2511_22951_amd import _native as N
+    dummy = C.c_void_p(0x1000)
+    b = N.Batch(1, 1000, 8, 16, 64, 0, 5.8, dummy, dummy)
+    sp = N.Spline(dummy, 64, 0, 1.5, 4.0 / 61)
+    big = N.Spline(dummy, 200, 0, 1.5, 4.0 / 197)
+    p = N.EAM(sp, sp, N.Spline(dummy, 64, 0, 5.0, 20.0 / 61), 5.5)
+    p_big = N.EAM(big, big, N.Spline(dummy, 64, 0, 5.0, 20.0 / 61), 5.5)
+    assert lib.md_density_jacobian_bytes(C.byref(b), C.byref(p)) == (8 * 1000 * 64 + 255) // 256 * 256
+    assert lib.md_density_jacobian_bytes(C.byref(b), C.byref(p_big)) == 0
+    nl = N.NList(dummy, dummy, 128, 4)
+    assert lib.md_eam_density_jacobian(C.byref(b), C.byref(p_big), dummy, C.byref(nl), dummy,
+                                       dummy, None) == N.MD_ERR_ARG
+    assert lib.md_eam_forces_jac(C.byref(b), C.byref(p), 0, dummy, dummy, C.byref(nl), None,
+                                 dummy, None, dummy, dummy, None) == N.MD_ERR_ARG
+    assert lib.md_eam_forces_jac(C.byref(b), C.byref(p_big), 0, dummy, dummy, C.byref(nl), dummy,
+                                 dummy, None, dummy, dummy, None) == N.MD_ERR_ARG
+    assert lib.md_eam_backward_jac(C.byref(b), C.byref(p), 0, dummy, C.byref(nl), dummy, None,
+                                   dummy, dummy, dummy, dummy, None) == N.MD_ERR_ARG
+    assert lib.md_force_loss_workspace_bytes(-1) == 0
+    assert lib.md_force_loss_workspace_bytes(300000) == 1024 * 8
+    assert lib.md_force_loss(-1, 0, dummy, dummy, dummy, None, dummy, None) == N.MD_ERR_ARG
+    assert lib.md_force_loss(10, 0, dummy, dummy, None, None, dummy, None) == N.MD_ERR_ARG
+    assert lib.md_force_loss(10, 0, None, dummy, dummy, None, dummy, None) == N.MD_ERR_ARG
+    assert lib.md_force_loss(10, 7, dummy, dummy, dummy, None, dummy, None) == N.MD_ERR_ARG
