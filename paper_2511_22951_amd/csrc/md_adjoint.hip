@@ -31,6 +31,7 @@ namespace {
 #define MD_ADJ_MAX_BINS 1024
 #define MD_ADJ_U 2        // list entries in flight per lane
 #define MD_ADJ_COPIES 8   // most copies of the phi and rho bins per wavefront
+#define MD_ADJ_COPIES_JAC 4  // the same with the density Jacobian (fewer adds per pair)
 #define MD_ADJ_LDS 49152  // LDS per block that the copies may fill
 #define MD_JAC_MAX_COEF 128  // density Jacobian: rows of 64 atoms in LDS (64 KiB)
 
@@ -455,7 +456,7 @@ int backward(const md_batch* b, const md_eam* p, md_precision prec, const double
     auto lds_of = [&](int c) {
       return ((size_t)nw * ((size_t)c * g.stride + g.n_emb) + g.n_rho + extra) * sizeof(double);
     };
-    g.copies = MD_ADJ_COPIES;
+    g.copies = jac ? MD_ADJ_COPIES_JAC : MD_ADJ_COPIES;
     while (g.copies > 1 && lds_of(g.copies) > MD_ADJ_LDS) g.copies >>= 1;
     const size_t lds = lds_of(g.copies);
     if (lds > 65536) return MD_ERR_ARG;  // fewer lanes per atom, or fewer coefficients

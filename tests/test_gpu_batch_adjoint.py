@@ -206,8 +206,8 @@ def test_adjoint_vjp_matches_oracle(md):
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
 def test_adjoint_vjp_every_lane_count(md, lanes, jac):
     """The adjoint at every lane count the list allows (a different number of bin copies
-    per wavefront fits the LDS at each: 8, 8, 8, 4, 2; 16 lanes leave about five list
-    entries per lane), with the second list visit and with the density Jacobian, against the
+    per wavefront fits the LDS at each: 8, 8, 8, 4, 2 with the second list visit, 4, 4, 4, 4,
+    2 with the density Jacobian; 16 lanes leave about five list entries per lane) against the
     oracle's chain-rule VJP, 1e-10 relative."""
     snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, n_snap=2, lanes=lanes, jac=jac)
     G = [mi.random_cotangent(len(s.pos), seed=60 + k) for k, s in enumerate(snaps)]
