@@ -546,11 +546,12 @@ __global__ __launch_bounds__(FBLOCK) void k_eam_density_f64(MD_EAM_DENSITY_ARGS(
 
 // Density pass for fixed positions whose density Jacobian jac[i][k] = d rhobar_i /
 // d c_rho_k is kept: rhobar_i = sum_k c_rho_k jac[i][k].  Each wavefront takes 64
-// consecutive atoms, four at a time: a group of 16 lanes reads one atom's row (lane q
-// entries q, q + 16, ...: one cache line per group and load) and adds it up by a group
-// butterfly; then the embedding as in the pair-loop pass with one atom per lane.
-// n_rho <= 128.
-template <typename R>
+// consecutive atoms, eight at a time: a group of 16 lanes reads one atom's row (lane q
+// entries q, q + 16, ...: one cache line per group and load; all NJ = ceil(n_rho / 16)
+// loads of two atoms issued together, entries past the row clamped to its last one with
+// a zero coefficient) and adds it up by a group butterfly; then the embedding as in the
+// pair-loop pass with one atom per lane.
+template <typename R, int NJ>
 __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_eam_density_jac(
     int n, double4* pos, const double* __restrict__ jac, const double* __restrict__ c_rho,
     int n_rho, const R* __restrict__ etab, TabGeom g, double* saved, uint4* rec,
@@ -562,19 +563,37 @@ __global__ __launch_bounds__(MD_ATOM_BLOCK) void k_eam_density_jac(
   if (a0 >= n) return;  // whole wavefronts
   const int na = min(MD_WAVE, n - a0);
   const int grp = lane >> 4, q = lane & 15;
-  double c[8];
+  double c[NJ];
+  int kk[NJ];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) c[j] = q + 16 * j < n_rho ? c_rho[q + 16 * j] : 0.0;
-#pragma unroll 2
-  for (int a = grp; a < na; a += 4) {
-    const double* row = jac + (size_t)(a0 + a) * n_rho;
-    double v = 0.0;
+  for (int j = 0; j < NJ; ++j) {
+    const int k = q + 16 * j;
+    c[j] = k < n_rho ? c_rho[k] : 0.0;
+    kk[j] = k < n_rho ? k : n_rho - 1;
+  }
+  for (int a = grp; a < na; a += 8) {
+    const int b2 = a + 4 < na ? a + 4 : a;  // the second atom (or the first again)
+    const double* r0 = jac + (size_t)(a0 + a) * n_rho;
+    const double* r1 = jac + (size_t)(a0 + b2) * n_rho;
+    double x0[NJ], x1[NJ];
     // streamed once per pass: kept out of the way of the force pass's cached records
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (q + 16 * j < n_rho) v = fma(c[j], __builtin_nontemporal_load(row + q + 16 * j), v);
-    v = md_group_sum<16>(v);
-    if (q == 0) wrho[a] = v;
+    for (int j = 0; j < NJ; ++j) {
+      x0[j] = __builtin_nontemporal_load(r0 + kk[j]);
+      x1[j] = __builtin_nontemporal_load(r1 + kk[j]);
+    }
+    double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      v0 = fma(c[j], x0[j], v0);
+      v1 = fma(c[j], x1[j], v1);
+    }
+    v0 = md_group_sum<16>(v0);
+    v1 = md_group_sum<16>(v1);
+    if (q == 0) {
+      wrho[a] = v0;
+      wrho[b2] = v1;  // b2 == a: the same value again
+    }
   }
   __builtin_amdgcn_wave_barrier();
   const double mine = lane < na ? wrho[lane] : 0.0;
@@ -1049,10 +1068,15 @@ int launch_eam(const md_batch& b, const md_eam& p, const char* tab, const md_tab
 #define MD_EAM_LAUNCH(EVB, TL_, E_, TH_)                                                          \
   do {                                                                                         \
     if (jac) {                                                                                 \
-      MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_jac<R>),                           \
-                      dim3((b.n_atoms + MD_ATOM_BLOCK - 1) / MD_ATOM_BLOCK), dim3(MD_ATOM_BLOCK), \
-                      0, st, b.n_atoms, (double4*)pos, jac, p.rho.coef, p.rho.ncoef, etab, g,  \
-                      saved, rec, ctl);                                                        \
+      const dim3 gj((b.n_atoms + MD_ATOM_BLOCK - 1) / MD_ATOM_BLOCK), bj(MD_ATOM_BLOCK);        \
+      if (p.rho.ncoef <= 64)                                                                   \
+        MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_jac<R, 4>), gj, bj, 0, st,        \
+                        b.n_atoms, (double4*)pos, jac, p.rho.coef, p.rho.ncoef, etab, g, saved, \
+                        rec, ctl);                                                             \
+      else                                                                                     \
+        MD_LAUNCH_TIMED(MD_KERNEL_EAM_DENSITY, (k_eam_density_jac<R, 8>), gj, bj, 0, st,        \
+                        b.n_atoms, (double4*)pos, jac, p.rho.coef, p.rho.ncoef, etab, g, saved, \
+                        rec, ctl);                                                             \
     } else if constexpr (std::is_same<R, float>::value) {                                      \
       if ((st_ = allow_big_lds((const void*)k_eam_density_f32<LANES, EVB, TL_, E_>, lds_d)))     \
         return st_;                                                                            \
