@@ -172,9 +172,11 @@ extern "C" int md_read_flags(const void* ctl, int* host_out, void* stream) {
   host_out[1] = h.step;
   host_out[2] = h.n_rebuilds;
   host_out[3] = h.max_nneigh;
-  if (h.flags & MD_FLAG_NONFINITE) return MD_ERR_NONFINITE;
+  // A void step (a list or carried records used past their validity) comes first: any
+  // non-finite position such a step produced is its consequence, not the cause.
   if (h.flags & MD_FLAG_STALE_LIST) return MD_ERR_STALE_LIST;
   if (h.flags & MD_FLAG_STALE_RECORDS) return MD_ERR_STALE_RECORDS;
+  if (h.flags & MD_FLAG_NONFINITE) return MD_ERR_NONFINITE;
   if (h.flags & MD_FLAG_NEIGH_OVERFLOW) return MD_ERR_NEIGH_OVERFLOW;
   if (h.flags & MD_FLAG_WALL) return MD_ERR_WALL;
   if (h.flags & MD_FLAG_TABLE_RANGE) return MD_ERR_TABLE_RANGE;
