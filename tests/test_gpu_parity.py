@@ -336,7 +336,9 @@ def test_carried_fp32_records_equal_converted(mdmod, pot, policy, graph):
     assert np.array_equal(a.state.velocities(), b.state.velocities())
     assert np.array_equal(a.energies(range(31)), b.energies(range(31)))
     st = b.state
-    r1 = torch.empty(16 * st.n, dtype=torch.uint8, device="cuda")
+    # all records at one point: the void step below also turns forces and positions
+    # non-finite, and the void step is what md_read_flags must report
+    r1 = torch.zeros(16 * st.n, dtype=torch.uint8, device="cuda")
     r2 = torch.empty_like(r1)
     drift = mdmod.drift_params(b.pos_alt, st.pos_ref, b.dt, b.half_skin, b.walls,
                                rec_in=r1, rec_out=r1)
@@ -358,6 +360,8 @@ def test_carried_fp32_records_equal_converted(mdmod, pot, policy, graph):
     with pytest.raises(mdmod.MDError) as e:
         st.check_flags()
     assert e.value.status == N.MD_ERR_STALE_RECORDS
+    if pot == "lj":  # coincident records: infinite pair forces, non-finite positions too
+        assert st.read_flags()[1]["flags"] & N.FLAG_NONFINITE
 
 
 def test_carried_records_after_steps_without_them(mdmod):
