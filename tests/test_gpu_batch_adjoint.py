@@ -307,6 +307,26 @@ def test_force_matching_gradient_matches_oracle_and_fd(md):
         assert abs(fd - got[k]) < 1e-5 * np.max(np.abs(got)), (k, fd, got[k])
 
 
+def test_force_matching_fp32_forward_gradient_near_fp64(md):
+    """The FP32-mixed forward (records and r^2 tables, Jacobian density pass) with the FP64
+    adjoint: loss within 1e-5 and gradient within 1e-5 of the largest entry of the all-FP64
+    epoch's, for the same snapshots, coefficients and reference forces."""
+    from paper_2511_22951_amd import fm
+    out = {}
+    for prec in (0, 1):
+        snaps, osnaps, grids, c_or, pot, batch = _fm_problem(md, n_snap=2, prec=prec)
+        ref_pot = md.EAMPotential.from_table(mi.tabulate_eam(mi.EAM_CU))
+        f_ref = batch.forces(ref_pot, saved=False).clone() if prec == 0 else out[0][2]
+        coef = torch.cat([c.clone() for c in pot.coef]).requires_grad_(True)
+        loss = fm.force_matching_loss(coef, batch, pot, f_ref)
+        loss.backward()
+        batch.state.check_flags()
+        out[prec] = (loss.item(), coef.grad.cpu().numpy(), f_ref)
+    (l64, g64, _), (l32, g32, _) = out[0], out[1]
+    assert abs(l32 - l64) <= 1e-5 * l64
+    assert np.max(np.abs(g32 - g64)) <= 1e-5 * np.max(np.abs(g64))
+
+
 def test_force_matching_backward_after_another_forward(md):
     """Two losses at different coefficients, then backward of the first: its gradient equals
     that of a forward-backward at the first coefficients alone, bit for bit."""
