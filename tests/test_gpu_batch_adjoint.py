@@ -265,6 +265,42 @@ def test_forces_with_jacobian_match_pair_pass(md, prec):
         assert (s1[0] - s0[0]).abs().max().item() <= 1e-5 * s0[0].abs().max().item()
 
 
+@pytest.mark.parametrize("lanes", [2, 4])
+def test_uneven_snapshots_jacobian_paths_match_oracle(md, lanes):
+    """Snapshots of 4^3, 6^3 and 5^3 cells (256, 864 and 500 atoms: ragged last tiles) in one
+    batch: the Jacobian density pass's forces and {rhobar} against the oracle's, and the
+    adjoint with and without the Jacobian against the oracle's VJP (1e-10 relative)."""
+    from paper_2511_22951_amd import fm
+    tab = mi.force_matching_tables()
+    noise = mi.coefficient_noise()
+    snaps = (mi.force_matching_snapshots(n_snap=1, cells=4, seed=901)
+             + mi.force_matching_snapshots(n_snap=1, cells=6, seed=902)
+             + mi.force_matching_snapshots(n_snap=1, cells=5, seed=903))
+    grids = tuple(oadj.Grid(tf.x_lo, tf.h, tf.K + 2) for tf in (tab.phi, tab.rho, tab.emb))
+    c_or = [osp.fit_table(tf) * noise[64 * b:64 * (b + 1)]
+            for b, tf in enumerate((tab.phi, tab.rho, tab.emb))]
+    osnaps = [oadj.Snapshot(s.pos, s.box, mi.EAM_CU.r_cut) for s in snaps]
+    fits = [md.md_spline_fit(tf.y, tf.h, tf.dy_lo, tf.dy_hi) for tf in (tab.phi, tab.rho, tab.emb)]
+    nz = torch.as_tensor(noise, device="cuda")
+    pot = md.EAMPotential(fits[0] * nz[:64], fits[1] * nz[64:128], fits[2] * nz[128:],
+                          tab.rho.x_lo, tab.rho.h, tab.emb.x_lo, tab.emb.h, mi.EAM_CU.r_cut)
+    G = [mi.random_cotangent(len(s.pos), seed=70 + k) for k, s in enumerate(snaps)]
+    want_vjp = np.concatenate(oadj.vjp(osnaps, c_or, grids, G))
+    want_f = np.concatenate([oadj.forces(s, c_or, grids)[0] for s in osnaps])
+    want_rb = np.concatenate([oadj.forces(s, c_or, grids)[1] for s in osnaps])
+    for jac in (False, True):
+        batch = fm.SnapshotBatch(snaps, mi.EAM_CU.r_cut + 0.3, lanes=lanes, density_jacobian=jac)
+        f = batch.forces(pot, saved=True)
+        order = np.argsort(batch.order_ids.cpu().numpy())
+        got_f = f.t().cpu().numpy()[order]
+        got_rb = batch.saved[0].cpu().numpy()[order]
+        assert np.max(np.abs(got_f - want_f)) <= 1e-10 * np.max(np.abs(want_f))
+        assert np.max(np.abs(got_rb - want_rb)) <= 1e-12 * np.max(np.abs(want_rb))
+        got = batch.backward(pot, batch.to_current_order(np.concatenate(G))).cpu().numpy()
+        batch.state.check_flags()
+        assert np.max(np.abs(got - want_vjp)) < 1e-10 * np.max(np.abs(want_vjp)), jac
+
+
 def test_backward_with_jacobian_equals_second_visit(md):
     """Both forms of the adjoint on the same forward state and cotangent: equal to 1e-13 of
     the largest gradient entry."""
