@@ -301,6 +301,36 @@ def test_uneven_snapshots_jacobian_paths_match_oracle(md, lanes):
         assert np.max(np.abs(got - want_vjp)) < 1e-10 * np.max(np.abs(want_vjp)), jac
 
 
+def test_jacobian_paths_with_100_coefficient_splines(md):
+    """Splines of 100 coefficients (the density pass's 8-loads-per-lane form, 51 KB Jacobian
+    rows in LDS, 200 phi|rho bins per copy): the Jacobian against the oracle's (1e-12), the
+    Jacobian forward's forces (1e-10) and both adjoint forms (1e-10) against the oracle."""
+    from paper_2511_22951_amd import fm
+    rr, qr = mi.FM_R_RANGE, mi.FM_RHO_RANGE
+    tab = mi.tabulate_eam(mi.EAM_CU, K=98, r_lo=rr[0], r_hi=rr[1], rho_lo=qr[0], rho_hi=qr[1])
+    snaps = mi.force_matching_snapshots(n_snap=2, cells=5, seed=911)
+    grids = tuple(oadj.Grid(tf.x_lo, tf.h, tf.K + 2) for tf in (tab.phi, tab.rho, tab.emb))
+    c_or = [osp.fit_table(tf) for tf in (tab.phi, tab.rho, tab.emb)]
+    assert all(len(c) == 100 for c in c_or)
+    osnaps = [oadj.Snapshot(s.pos, s.box, mi.EAM_CU.r_cut) for s in snaps]
+    pot = md.EAMPotential.from_table(tab)
+    G = [mi.random_cotangent(len(s.pos), seed=75 + k) for k, s in enumerate(snaps)]
+    want_vjp = np.concatenate(oadj.vjp(osnaps, c_or, grids, G))
+    want_f = np.concatenate([oadj.forces(s, c_or, grids)[0] for s in osnaps])
+    want_j = np.concatenate([oadj.density_jacobian(s, grids[1]) for s in osnaps])
+    for jac in (False, True):
+        batch = fm.SnapshotBatch(snaps, mi.EAM_CU.r_cut + 0.3, density_jacobian=jac)
+        order = np.argsort(batch.order_ids.cpu().numpy())
+        if jac:
+            J = batch.jacobian(pot).cpu().numpy()[order]
+            assert np.max(np.abs(J - want_j)) <= 1e-12 * np.max(np.abs(want_j))
+        f = batch.forces(pot, saved=True)
+        assert np.max(np.abs(f.t().cpu().numpy()[order] - want_f)) <= 1e-10 * np.max(np.abs(want_f))
+        got = batch.backward(pot, batch.to_current_order(np.concatenate(G))).cpu().numpy()
+        batch.state.check_flags()
+        assert np.max(np.abs(got - want_vjp)) < 1e-10 * np.max(np.abs(want_vjp)), jac
+
+
 def test_backward_with_jacobian_equals_second_visit(md):
     """Both forms of the adjoint on the same forward state and cotangent: equal to 1e-13 of
     the largest gradient entry."""
